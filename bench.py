@@ -1,0 +1,245 @@
+"""Benchmark: veff_grad throughput (atom*beads/s) on one MI355X.
+
+One step = one veff_grad call over one path (binning, pair forces of beads 1..N-1,
+FP64 residuals and spring energy, pair Hessian-vector products, FP64 gradient assembly
+and V_eff reduction), inputs already resident in HBM.  Default workload: the
+membrane-shaped system, 150,000 atoms x 16 beads, cutoff 1.2 nm.
+
+Prints ONE JSON line with the throughput, the roofline of the dominant kernel (the pair
+Hessian-vector kernel, FP32 ALU-bound), the finite-difference comparison path, and the
+FP64 CPU oracle timed on a bounded sample of the same workload.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config cfg4]
+                    [--no-cpu-baseline] [--no-fd] [--no-graph]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "veff_grad atom·beads/s, analytic HVP vs finite-diff HVP, 1 MI355X"
+PEAK_FP32_TFLOPS = 157.3      # MI355X FP32 vector (published)
+PEAK_HBM_GBS = 8000.0
+# Algorithmic FLOPs per unique within-cutoff pair (FMA = 2, rsqrt = 1, others 1),
+# counted from the pair formulas with Newton's third law (each pair once).
+FLOP_FORCE_PAIR = 34
+FLOP_HVP_PAIR = 60
+PAIR_SRC = os.path.join(ROOT, "paper_2501_11962_amd", "csrc", "kernels_pair.hip")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def unique_pairs(system, X):
+    """Unique non-excluded atom pairs closer than the cutoff (minimum image), counted
+    with a periodic k-d tree; bonded 1-2/1-3 pairs are always within the cutoff here and
+    are subtracted."""
+    from scipy.spatial import cKDTree
+    box = np.asarray(system["box"], np.float64)
+    Y = X - box * np.floor(X / box)
+    Y = np.minimum(Y, np.nextafter(box, 0))
+    t = cKDTree(Y, boxsize=box)
+    n = int(t.count_neighbors(t, system["rc"]))
+    Q = system["Q"]
+    within = (n - Q) // 2
+    # excluded pairs: bond-graph distance 1 or 2
+    nb = [[] for _ in range(Q)]
+    for i, j in np.asarray(system["bonds"]).reshape(-1, 2):
+        nb[i].append(int(j))
+        nb[j].append(int(i))
+    ex = set()
+    for i in range(Q):
+        for j in nb[i]:
+            ex.add((min(i, j), max(i, j)))
+            for k in nb[j]:
+                if k != i:
+                    ex.add((min(i, k), max(i, k)))
+    return within - len(ex)
+
+
+def traffic_from_profiles(workload):
+    """HBM bytes per launch of the HVP pair kernel measured by rocprofv3 counters, if the
+    committed summary was taken on the current kernel source; else None."""
+    p = os.path.join(ROOT, "profiles", f"traffic_pair_hvp_{workload}.json")
+    if not os.path.exists(p):
+        return None
+    d = json.load(open(p))
+    h = hashlib.sha256(open(PAIR_SRC, "rb").read()).hexdigest()
+    if d.get("kernel_source_sha256") != h:
+        return None
+    return d.get("bytes_per_launch")
+
+
+def cpu_baseline(system, R, beads):
+    """FP64 cell-list oracle (all host threads) on the first `beads` beads of the path."""
+    from oracle import cl
+    from oracle import path as OP
+    m = cl.CellModel(system)
+    sub = np.ascontiguousarray(R[:beads])
+    t0 = time.perf_counter()
+    OP.veff_grad(m, sub)
+    dt = time.perf_counter() - t0
+    return dict(value=system["Q"] * beads / dt, unit="atom·beads/s", cores=cl.max_threads(),
+                kind="oracle",
+                sample=f"veff_grad of the first {beads} beads of the same path "
+                       f"({beads - 1} force + {beads - 1} Hessian-vector passes over "
+                       f"{system['Q']} atoms), {dt:.1f} s wall")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="cfg4")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-beads", type=int, default=3)
+    ap.add_argument("--no-fd", action="store_true")
+    ap.add_argument("--fd-h", type=float, default=1e-4)
+    ap.add_argument("--no-graph", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (--gpus {args.gpus} requested): this build "
+              f"has no multi-GPU path; run with --gpus 1.", flush=True)
+        sys.exit(2)
+
+    import torch
+    import workloads as W
+    import paper_2501_11962_amd as mop
+
+    t0 = time.perf_counter()
+    system, R = W.make_config(args.config)
+    N, Q = R.shape[0], system["Q"]
+    log(f"[bench] workload {args.config}: Q={Q} N={N} rc={system['rc']} ({time.perf_counter() - t0:.1f} s)")
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    Rt = torch.from_numpy(R).to(dev)
+    ctx = mop.Context()
+    plan = mop.Plan(mop.System(ctx, system), N)
+    G = torch.empty_like(Rt)
+    v = torch.empty(1, dtype=torch.float64, device=dev)
+
+    def step():
+        mop.veff_grad(plan, Rt, 0, 0.0, G, v)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    st = plan.status()
+    if st:
+        raise SystemExit(f"device status {st} after warm-up")
+    log(f"[bench] warm-up done, V_eff = {float(v[0]):.6e}")
+
+    # eager timing
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(args.steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms_eager = e0.elapsed_time(e1) / args.steps
+    log(f"[bench] eager: {ms_eager:.3f} ms/step")
+
+    # the whole call captured once in a graph and replayed
+    ms_graph = None
+    if not args.no_graph:
+        try:
+            g = torch.cuda.CUDAGraph()
+            cs = torch.cuda.Stream()
+            cs.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.graph(g, stream=cs):
+                ctx.set_stream()
+                step()
+            ctx.set_stream()
+            torch.cuda.synchronize()
+            Gref = G.clone()
+            g.replay()
+            torch.cuda.synchronize()
+            if not torch.equal(G, Gref) and not torch.allclose(G, Gref, rtol=1e-6, atol=0):
+                raise RuntimeError("graph replay differs from eager")
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(args.steps):
+                g.replay()
+            e1.record()
+            torch.cuda.synchronize()
+            ms_graph = e0.elapsed_time(e1) / args.steps
+            log(f"[bench] graph: {ms_graph:.3f} ms/step")
+        except Exception as ex:  # graph capture is optional; eager timing stands
+            log(f"[bench] graph capture skipped: {ex}")
+            ctx.set_stream()
+    ms = ms_graph if ms_graph is not None else ms_eager
+
+    # per-phase times (HIP events between phases, same stream)
+    acc = None
+    for _ in range(args.steps):
+        _, _, ph = mop.veff_grad_timed(plan, Rt, 0, 0.0, G, v)
+        acc = ph if acc is None else {k: acc[k] + ph[k] for k in acc}
+    phases = {k: acc[k] / args.steps for k in acc}
+    log(f"[bench] phases (ms): {json.dumps({k: round(x, 4) for k, x in phases.items()})}")
+
+    # finite-difference comparison path (eq. 5 as printed: 3 force passes per bead)
+    fd = None
+    if not args.no_fd:
+        for _ in range(2):
+            mop.veff_grad(plan, Rt, 1, args.fd_h, G, v)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(args.steps):
+            mop.veff_grad(plan, Rt, 1, args.fd_h, G, v)
+        e1.record()
+        torch.cuda.synchronize()
+        ms_fd = e0.elapsed_time(e1) / args.steps
+        fd = dict(value=Q * N / (ms_fd * 1e-3), ms_per_step=ms_fd, fd_h_nm=args.fd_h,
+                  speedup_analytic_over_fd=ms_fd / ms)
+        log(f"[bench] FD path: {ms_fd:.3f} ms/step")
+
+    # roofline of the dominant kernel
+    npairs = unique_pairs(system, R[0])
+    pair_beads = N - 1
+    flops_hvp = FLOP_HVP_PAIR * npairs * pair_beads
+    flops_force = FLOP_FORCE_PAIR * npairs * pair_beads
+    t_hvp, t_force = phases["hvp"] * 1e-3, phases["force"] * 1e-3
+    ach = flops_hvp / t_hvp / 1e12
+    traffic = traffic_from_profiles(args.config)
+    roof = dict(bound="alu", kernel="k_pair<1> (pair Hessian-vector product)",
+                achieved=round(ach, 3), peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
+                frac=round(ach / PEAK_FP32_TFLOPS, 4), traffic=traffic,
+                algorithmic_flops_per_launch=flops_hvp, pairs_per_bead=npairs,
+                launch_ms=round(phases["hvp"], 4),
+                force_kernel=dict(achieved=round(flops_force / t_force / 1e12, 3),
+                                  launch_ms=round(phases["force"], 4)),
+                whole_step_tflops=round((flops_hvp + flops_force) / (ms * 1e-3) / 1e12, 3))
+
+    out = dict(metric=METRIC, value=Q * N / (ms * 1e-3), unit="atom·beads/s", n_gpus=1,
+               steps=args.steps, warmup=args.warmup, ms_per_step=ms, higher_is_better=True,
+               scaling="weak", vs_baseline=None, dtype="f32",
+               data="synthetic",
+               config=dict(workload=f"{args.config}: {system['name']} Q={Q} atoms x N={N} beads, "
+                                    f"rc={system['rc']} nm, analytic HVP",
+                           Q=Q, N=N, rc=system["rc"], box=[float(b) for b in system["box"]],
+                           graph=ms_graph is not None, ms_eager=ms_eager,
+                           precision="FP32 pair terms from 32-bit fixed-point coordinates; "
+                                     "FP64 bonds, residuals, reductions, gradient"),
+               roofline=roof, fd=fd, phases_ms=phases)
+    if not args.no_cpu_baseline:
+        log(f"[bench] CPU oracle on {args.cpu_beads} beads ...")
+        out["cpu_baseline"] = cpu_baseline(system, R, args.cpu_beads)
+        log(f"[bench] CPU oracle: {out['cpu_baseline']['value']:.3e} atom*beads/s")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,213 @@
+/*
+ * mop.h -- C ABI of the MI355X (gfx950) library for the Onsager-Machlup path gradient
+ * used by path molecular dynamics and metadynamics of paths.
+ *
+ * The operations follow the paper's statement of the problem (section 1.1):
+ *   - a system of Q atoms with potential U and force F = -grad U (eq. 1);
+ *   - a path of N beads R^1 .. R^N, each a full copy of the system (Fig. 1);
+ *   - the effective potential of eq. (3)
+ *         V_eff = U(R^1) + sum_{n=1}^{N-1} sum_i K_i/2 |d^n_i|^2,
+ *         d^n = mi(R^{n+1} - R^n) - c F(R^n),  K_i = m_i nu/(2 dt),  c_i = dt/(m_i nu)
+ *     (the rest length is read as L^n = c F^n, the only reading under which eqs. 5-7
+ *     are the gradient of eq. 3; mi = minimum image);
+ *   - its gradient G = grad V_eff = -F_eff of eqs. (5)-(7), with the finite-difference
+ *     Hessian term of eq. (5) replaced by the exact Hessian-vector product, or, for
+ *     comparison, computed as in eq. (5).
+ *
+ * The potential is the short-range part of a molecular force field: Lennard-Jones
+ * (Lorentz-Berthelot mixing) plus reaction-field electrostatics, both shifted-force at
+ * r_cut, harmonic bonds, and exclusion of 1-2/1-3 bonded pairs; orthorhombic periodic
+ * box with r_cut < min(box)/2.  Units: nm, ps, amu, kJ/mol, e.
+ *
+ * Precision: pair forces and pair Hessian-vector products are evaluated in FP32 from
+ * 32-bit fixed-point coordinates (exact minimum image); bonds, residuals, energies and
+ * the gradient assembly are FP64.
+ *
+ * Conventions for every compute call:
+ *   - Array arguments are DEVICE pointers to C-contiguous arrays, bead-major:
+ *     [beads][Q][3].  The caller owns all inputs, outputs and the workspace.
+ *   - Calls are asynchronous on the stream given to mop_ctx_create, allocate nothing
+ *     and never synchronise with the host, so they can be captured in a hipGraph.
+ *   - Return value 0 = MOP_OK; a negative value is a synchronous argument error
+ *     detected on the host, in which case nothing was enqueued.
+ *   - Errors found on the device (non-finite result, exhausted capacity) set bits of a
+ *     status word inside the workspace; read it with mop_status after the work has
+ *     finished.  Outputs are unspecified when a bit is set.
+ */
+#ifndef MOP_H
+#define MOP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------------------ */
+#define MOP_OK 0
+#define MOP_EINVAL (-1)     /* null pointer, bad size, bad option */
+#define MOP_ECUTOFF (-2)    /* r_cut >= min(box)/2 or r_cut <= 0 */
+#define MOP_ETYPE (-3)      /* type index out of range or too many types */
+#define MOP_EHIP (-4)       /* a HIP runtime call failed (e.g. no device) */
+#define MOP_ENOMEM (-5)     /* device allocation failed (create calls only) */
+#define MOP_ETOPOLOGY (-6)  /* bonds do not form linear chains; pass excl_mol/excl_pos */
+#define MOP_ESIZE (-7)      /* more beads or paths than the plan or batch was made for */
+
+/* bits of the device status word (mop_status) */
+#define MOP_DEV_NONFINITE 1 /* a force, residual or gradient component is not finite */
+#define MOP_DEV_CAPACITY 2  /* a neighbour-search buffer overflowed (re-plan) */
+
+typedef struct mop_ctx_s* mop_ctx;
+typedef struct mop_system_s* mop_system;
+typedef struct mop_plan_s* mop_plan;
+typedef struct mop_batch_s* mop_batch;
+
+/*
+ * System description.  All pointers are HOST pointers; the arrays are copied by
+ * mop_system_create and may be freed afterwards.
+ *   Q               number of atoms (>= 1)
+ *   box             orthorhombic box lengths (nm)
+ *   mass[Q]         amu (> 0);  charge[Q] e;  type[Q] in [0, ntypes)
+ *   sigma/epsilon   per-type LJ parameters [ntypes] (ntypes <= 16), mixed by
+ *                   Lorentz-Berthelot; epsilon = 0 switches LJ off for a type
+ *   bond_ij[2*nbonds], bond_r0[nbonds] (nm), bond_k[nbonds] (kJ/mol/nm^2)
+ *   excl_mol/excl_pos[Q]  molecule id and position along a linear chain; pairs of the
+ *                   same molecule whose positions differ by at most 2 are excluded.
+ *                   NULL: derived from the bonds, which must then form linear chains.
+ *   r_cut (nm), eps_rf, eps_r (reaction field: k_rf = (eps_rf - eps_r) /
+ *                   ((2 eps_rf + eps_r) r_cut^3)), dt (ps), nu (1/ps)
+ */
+typedef struct {
+    int32_t Q;
+    double box[3];
+    const double* mass;
+    const double* charge;
+    const int32_t* type;
+    int32_t ntypes;
+    const double* sigma;
+    const double* epsilon;
+    int32_t nbonds;
+    const int32_t* bond_ij;
+    const double* bond_r0;
+    const double* bond_k;
+    const int32_t* excl_mol;
+    const int32_t* excl_pos;
+    double r_cut, eps_rf, eps_r, dt, nu;
+} mop_system_desc;
+
+/*
+ * Neighbour-search options of a plan (0 = default for every field).
+ *   col_width   width (nm) of the x-y columns atoms are binned into; 8-atom clusters
+ *               are cut along z inside each column.  Default 0.5 nm.
+ *   zbin        height (nm) of the z bins used to sort columns.  Default 0.1 nm.
+ *   waves       waves per workgroup of the pair kernels (1, 2, 4, 8).  Default 4.
+ */
+typedef struct {
+    double col_width;
+    double zbin;
+    int32_t waves;
+    int32_t flags;
+} mop_plan_opts;
+
+/* Host-only validation of a system description (no device needed).  Returns MOP_OK,
+ * MOP_EINVAL, MOP_ECUTOFF, MOP_ETYPE or MOP_ETOPOLOGY. */
+int mop_system_check(const mop_system_desc* desc);
+
+/* Context on HIP device `device`, issuing work on `hip_stream` (a hipStream_t; NULL is
+ * the null stream).  MOP_EHIP when the device cannot be used. */
+int mop_ctx_create(int device, void* hip_stream, mop_ctx* out);
+int mop_ctx_set_stream(mop_ctx ctx, void* hip_stream);
+void mop_ctx_destroy(mop_ctx ctx);
+
+/* Copy a system to the device (constants, type-pair tables, bond lists, exclusion
+ * keys).  Allocates device memory. */
+int mop_system_create(mop_ctx ctx, const mop_system_desc* desc, mop_system* out);
+void mop_system_destroy(mop_system sys);
+
+/* Plan for paths of up to `max_beads` beads of one system (also the maximum B of
+ * bead_forces / bead_hvp).  opts may be NULL.  Allocates device memory. */
+int mop_plan_create(mop_system sys, int32_t max_beads, const mop_plan_opts* opts, mop_plan* out);
+void mop_plan_destroy(mop_plan plan);
+
+/* Workspace bytes a call on this plan needs (for any bead count up to max_beads and
+ * either gradient mode).  The caller allocates it (256-byte aligned) and passes it to
+ * every call; calls that share a workspace must not overlap in time. */
+int mop_workspace_size(mop_plan plan, size_t* bytes);
+
+/*
+ * Physical forces of B independent configurations (the do_force call of section 2.1):
+ *   R  [B][Q][3] double in;   F [B][Q][3] float out, F = -grad U(R^b)
+ *   U  [B] double out (potential energy per configuration) or NULL
+ */
+int bead_forces(mop_plan plan, const double* R, int32_t B, float* F, double* U, void* ws);
+
+/*
+ * Hessian-vector products HV^b = H(R^b) V^b, H = Hessian of U (the quantity the
+ * finite-difference term of eq. 5 approximates, as -1/2 H eta):
+ *   R, V [B][Q][3] double in;   HV [B][Q][3] float out
+ */
+int bead_hvp(mop_plan plan, const double* R, const double* V, int32_t B, float* HV, void* ws);
+
+/*
+ * Effective potential of eq. (3) for one path R [N][Q][3] (N >= 1).  Each output is a
+ * single device double, or NULL: veff = u1 + espring, u1 = U(R^1), espring = spring sum.
+ */
+int veff_energy(mop_plan plan, const double* R, int32_t N, double* veff, double* u1,
+                double* espring, void* ws);
+
+/*
+ * Gradient G [N][Q][3] (device double out) of V_eff for one path, and V_eff (one device
+ * double, or NULL).  mode 0: exact Hessian-vector products.  mode 1: the
+ * finite-difference term of eq. (5), [F(R + eps d) - F(R - eps d)]/(4 eps), with
+ * eps = fd_h / max_i |d^n_i| per bead (fd_h in nm, > 0), each displaced configuration
+ * re-binned.  G = -F_eff of eqs. (5)-(7).
+ */
+int veff_grad(mop_plan plan, const double* R, int32_t N, double* G, double* veff,
+              int32_t mode, double fd_h, void* ws);
+
+/*
+ * Batch of P independent paths (each with its own plan/system and bead count),
+ * evaluated together: every phase of all paths is one kernel launch.  Paths are packed
+ * back to back in one buffer: path p occupies N_p*Q_p*3 doubles starting at element
+ * sum_{q<p} N_q*Q_q*3 of R (and of G).
+ */
+int mop_batch_create(int32_t P, const mop_plan* plans, const int32_t* N, mop_batch* out);
+void mop_batch_destroy(mop_batch batch);
+int mop_batch_workspace_size(mop_batch batch, size_t* bytes);
+/* veff [P] device doubles or NULL; mode / fd_h as in veff_grad */
+int mop_batch_veff_grad(mop_batch batch, const double* R, double* G, double* veff,
+                        int32_t mode, double fd_h, void* ws);
+
+/* Synchronise the context stream and read the device status word of a workspace that
+ * was used with `plan` (bits MOP_DEV_*). */
+int mop_status(mop_plan plan, const void* ws, int32_t* device_status);
+/* Clear the status word (asynchronous, on the context stream). */
+int mop_status_clear(mop_plan plan, void* ws);
+
+/*
+ * Profiling variant of veff_grad: the same work, with HIP events recorded on the
+ * context stream between phases; waits for completion and writes the elapsed time of
+ * each phase in milliseconds to phase_ms[MOP_NPHASES] (host array).  Synchronises the
+ * host, so it must not be captured in a graph.
+ */
+#define MOP_NPHASES 6
+#define MOP_PHASE_BIN 0       /* fixed point, histogram, scans, scatter, padding */
+#define MOP_PHASE_FORCE 1     /* pair-force kernel, beads 1..N-1 (energy of bead 1) */
+#define MOP_PHASE_RESID 2     /* residuals, spring energy, FP32 copy of d */
+#define MOP_PHASE_HVP 3       /* pair Hessian-vector kernel (mode 0) */
+#define MOP_PHASE_FD 4        /* re-binning + two force passes (mode 1) */
+#define MOP_PHASE_ASSEMBLE 5  /* gradient assembly and V_eff reduction */
+int veff_grad_timed(mop_plan plan, const double* R, int32_t N, double* G, double* veff,
+                    int32_t mode, double fd_h, void* ws, float* phase_ms);
+
+/* Human-readable text of a return code. */
+const char* mop_strerror(int code);
+
+/* Fixed-point geometry of a plan, for tests: column counts, z bins, slot capacity. */
+int mop_plan_info(mop_plan plan, int32_t* ncx, int32_t* ncy, int32_t* nzb, int32_t* slots);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MOP_H */

@@ -1,0 +1,118 @@
+// Device helpers shared by the kernel files.
+#pragma once
+
+#include "mop_internal.h"
+
+namespace mop {
+
+// Segment (path) that owns logical block `blk`; block prefixes are uniform, so this
+// is a short scalar loop.
+__device__ __forceinline__ int find_seg(const Launch& L, int blk) {
+    int p = 0;
+    while (p + 1 < L.nseg && L.pf[p + 1] <= blk) ++p;
+    return p;
+}
+
+template <class T>
+__device__ __forceinline__ T* wsp(char* ws, size_t off) {
+    return reinterpret_cast<T*>(ws + off);
+}
+
+// Minimum image of a coordinate difference in a periodic box of length L.
+__device__ __forceinline__ double min_img(double d, double L) { return d - L * rint(d / L); }
+
+// Fixed-point coordinate: the box [0, L) maps onto [0, 2^32); wrap-around of unsigned
+// differences is then exactly the minimum image.
+__device__ __forceinline__ uint32_t to_fixed(double x, double L) {
+    double t = x / L;
+    t -= floor(t);
+    const double v = t * 4294967296.0;
+    return v >= 4294967295.0 ? 0xFFFFFFFFu : static_cast<uint32_t>(v);
+}
+
+// Column / z-bin index of a fixed-point coordinate among n equal bins.
+__device__ __forceinline__ int fixed_bin(uint32_t u, int n) {
+    return static_cast<int>((static_cast<uint64_t>(u) * static_cast<uint64_t>(n)) >> 32);
+}
+
+// Orders the wave's LDS traffic: all earlier LDS accesses of the wave complete before
+// any later one is issued, and the compiler moves no memory access across it.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+__device__ __forceinline__ int wave_incl_scan(int v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int t = __shfl_up(v, d, 64);
+        if (lane >= d) v += t;
+    }
+    return v;
+}
+
+// Block-wide sum of a double (blockDim.x == EWB), result valid in thread 0.
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    __syncthreads();
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) s += sh[k];
+    return s;
+}
+
+// Harmonic bonds of atom i in FP64 (each bond is listed for both of its atoms).
+// Adds the force on i to f; adds k/2 (r - r0)^2 of bonds with partner j > i to *e.
+__device__ __forceinline__ void bond_force(const SysDev& s, const double* Rb, const double* Db,
+                                           double eps, int i, double f[3], double* e) {
+    const int k0 = s.bstart[i], k1 = s.bstart[i + 1];
+    if (k0 == k1) return;
+    double xi[3];
+    for (int a = 0; a < 3; ++a) {
+        xi[a] = Rb[3 * (size_t)i + a];
+        if (Db) xi[a] += eps * Db[3 * (size_t)i + a];
+    }
+    for (int k = k0; k < k1; ++k) {
+        const int j = s.bpart[k];
+        double d[3], r2 = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            double xj = Rb[3 * (size_t)j + a];
+            if (Db) xj += eps * Db[3 * (size_t)j + a];
+            d[a] = min_img(xj - xi[a], s.L[a]);
+            r2 += d[a] * d[a];
+        }
+        const double r = sqrt(r2), kb = s.bk[k], r0 = s.br0[k];
+        const double g = kb * (1.0 - r0 / r);
+        for (int a = 0; a < 3; ++a) f[a] += g * d[a];
+        if (e && j > i) *e += 0.5 * kb * (r - r0) * (r - r0);
+    }
+}
+
+// Bond part of (H v)_i in FP64: sum_k g (v_i - v_j) + h (d . (v_i - v_j)) d,
+// g = k (1 - r0/r), h = k r0 / r^3.
+__device__ __forceinline__ void bond_hvp(const SysDev& s, const double* Rb, const double* Vb,
+                                         int i, double hv[3]) {
+    const int k0 = s.bstart[i], k1 = s.bstart[i + 1];
+    for (int k = k0; k < k1; ++k) {
+        const int j = s.bpart[k];
+        double d[3], dv[3], r2 = 0.0, sd = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            d[a] = min_img(Rb[3 * (size_t)j + a] - Rb[3 * (size_t)i + a], s.L[a]);
+            dv[a] = Vb[3 * (size_t)i + a] - Vb[3 * (size_t)j + a];
+            r2 += d[a] * d[a];
+            sd += d[a] * dv[a];
+        }
+        const double r = sqrt(r2), kb = s.bk[k], r0 = s.br0[k];
+        const double g = kb * (1.0 - r0 / r);
+        const double h = kb * r0 / (r2 * r);
+        for (int a = 0; a < 3; ++a) hv[a] += g * dv[a] + h * sd * d[a];
+    }
+}
+
+}  // namespace mop

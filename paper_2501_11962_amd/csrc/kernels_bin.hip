@@ -1,0 +1,190 @@
+// Binning of every pair bead of every path of a call into the column/cluster layout.
+//
+// Per bead: wrap coordinates into 32-bit fixed point, histogram atoms over
+// (column, z bin), scan bins inside each column, scan padded column counts, scatter
+// atoms into slot order, and fill each column's padding slots.  The counting sort
+// replaces the pair search of the physical force routine (do_force, section 2.1).
+// HBM-bound, O(Q) per bead.
+#include "device_common.h"
+#include "launch.h"
+
+namespace mop {
+
+// Zero the bin histograms and the per-bead max |d|^2 of every segment.
+__global__ void __launch_bounds__(EWB) k_zero(const SegDev* __restrict__ segs, Launch L, char* ws,
+                                              int zero_dmax) {
+    const int blk = blockIdx.x;
+    const int p = find_seg(L, blk);
+    const SegDev& sg = segs[p];
+    const size_t idx = (size_t)(blk - L.pf[p]) * EWB + threadIdx.x;
+    const size_t n1 = (size_t)L.nb[p] * sg.s.ncol * sg.s.nzb;
+    if (idx < n1) {
+        wsp<int>(ws, sg.o_bincnt)[idx] = 0;
+    } else if (zero_dmax && idx - n1 < (size_t)sg.maxN) {
+        wsp<unsigned long long>(ws, sg.o_dmax)[idx - n1] = 0ull;
+    }
+}
+
+// Fixed-point coordinates, bin key and rank inside the bin.  fdsign != 0 bins the
+// displaced configuration R^b + fdsign * eps_b d^b of the finite-difference term.
+__global__ void __launch_bounds__(EWB) k_bin_count(const SegDev* __restrict__ segs, Launch L,
+                                                   char* ws, const double* __restrict__ R,
+                                                   int fdsign, double fdh) {
+    const int blk = blockIdx.x;
+    const int p = find_seg(L, blk);
+    const SegDev& sg = segs[p];
+    const int local = blk - L.pf[p];
+    const int b = local / sg.bpb;
+    const int i = (local - b * sg.bpb) * EWB + threadIdx.x;
+    const int Q = sg.s.Q;
+    if (i >= Q) return;
+    const double* r = R + sg.roff + ((size_t)b * Q + i) * 3;
+    double x = r[0], y = r[1], z = r[2];
+    if (fdsign != 0) {
+        const double m2 = __longlong_as_double(
+            (long long)wsp<unsigned long long>(ws, sg.o_dmax)[b]);
+        const double eps = m2 > 0.0 ? fdsign * fdh / sqrt(m2) : 0.0;
+        const double* d = wsp<const double>(ws, sg.o_d64) + ((size_t)b * Q + i) * 3;
+        x += eps * d[0];
+        y += eps * d[1];
+        z += eps * d[2];
+    }
+    const uint32_t ux = to_fixed(x, sg.s.L[0]), uy = to_fixed(y, sg.s.L[1]), uz = to_fixed(z, sg.s.L[2]);
+    const int col = fixed_bin(ux, sg.s.ncx) * sg.s.ncy + fixed_bin(uy, sg.s.ncy);
+    const int key = col * sg.s.nzb + fixed_bin(uz, sg.s.nzb);
+    int* cnt = wsp<int>(ws, sg.o_bincnt) + (size_t)b * sg.s.ncol * sg.s.nzb;
+    const int rank = atomicAdd(cnt + key, 1);
+    wsp<uint4>(ws, sg.o_atomu)[(size_t)b * Q + i] = make_uint4(ux, uy, uz, (uint32_t)key);
+    wsp<int>(ws, sg.o_rank)[(size_t)b * Q + i] = rank;
+}
+
+// Exclusive scan of the z bins of each column; column totals.
+__global__ void __launch_bounds__(EWB) k_bin_colscan(const SegDev* __restrict__ segs, Launch L, char* ws) {
+    const int blk = blockIdx.x;
+    const int p = find_seg(L, blk);
+    const SegDev& sg = segs[p];
+    const int t = (blk - L.pf[p]) * EWB + threadIdx.x;
+    const int ncol = sg.s.ncol, nzb = sg.s.nzb;
+    if (t >= L.nb[p] * ncol) return;
+    const int b = t / ncol, col = t - b * ncol;
+    const int* cnt = wsp<const int>(ws, sg.o_bincnt) + ((size_t)b * ncol + col) * nzb;
+    int* off = wsp<int>(ws, sg.o_binoff) + ((size_t)b * ncol + col) * (nzb + 1);
+    int run = 0;
+    for (int z = 0; z < nzb; ++z) {
+        off[z] = run;
+        run += cnt[z];
+    }
+    off[nzb] = run;
+    wsp<int>(ws, sg.o_colcnt)[(size_t)b * ncol + col] = run;
+}
+
+// Exclusive scan of the padded (multiple of 8) column counts of one bead per block.
+constexpr int CSB = 1024;
+__global__ void __launch_bounds__(CSB) k_bin_colstart(const SegDev* __restrict__ segs, Launch L, char* ws) {
+    __shared__ int sh[CSB];
+    const int blk = blockIdx.x;
+    const int p = find_seg(L, blk);
+    const SegDev& sg = segs[p];
+    const int b = blk - L.pf[p];
+    const int ncol = sg.s.ncol;
+    const int* cc = wsp<const int>(ws, sg.o_colcnt) + (size_t)b * ncol;
+    int* cs = wsp<int>(ws, sg.o_colstart) + (size_t)b * (ncol + 1);
+    const int per = (ncol + CSB - 1) / CSB;
+    const int c0 = threadIdx.x * per, c1 = min(ncol, c0 + per);
+    int sum = 0;
+    for (int c = c0; c < c1; ++c) sum += (cc[c] + 7) & ~7;
+    sh[threadIdx.x] = sum;
+    __syncthreads();
+    for (int d = 1; d < CSB; d <<= 1) {
+        const int v = threadIdx.x >= d ? sh[threadIdx.x - d] : 0;
+        __syncthreads();
+        sh[threadIdx.x] += v;
+        __syncthreads();
+    }
+    int run = sh[threadIdx.x] - sum;
+    for (int c = c0; c < c1; ++c) {
+        cs[c] = run;
+        run += (cc[c] + 7) & ~7;
+    }
+    if (threadIdx.x == CSB - 1) cs[ncol] = sh[CSB - 1];
+}
+
+// Scatter atoms into slot order.
+__global__ void __launch_bounds__(EWB) k_bin_scatter(const SegDev* __restrict__ segs, Launch L, char* ws) {
+    const int blk = blockIdx.x;
+    const int p = find_seg(L, blk);
+    const SegDev& sg = segs[p];
+    const int local = blk - L.pf[p];
+    const int b = local / sg.bpb;
+    const int i = (local - b * sg.bpb) * EWB + threadIdx.x;
+    const int Q = sg.s.Q, ncol = sg.s.ncol, nzb = sg.s.nzb, S = sg.s.S;
+    if (i >= Q) return;
+    const uint4 u = wsp<const uint4>(ws, sg.o_atomu)[(size_t)b * Q + i];
+    const int key = (int)u.w;
+    const int col = key / nzb, zb = key - col * nzb;
+    const int slot = wsp<const int>(ws, sg.o_colstart)[(size_t)b * (ncol + 1) + col] +
+                     wsp<const int>(ws, sg.o_binoff)[((size_t)b * ncol + col) * (nzb + 1) + zb] +
+                     wsp<const int>(ws, sg.o_rank)[(size_t)b * Q + i];
+    wsp<uint4>(ws, sg.o_upos)[(size_t)b * S + slot] =
+        make_uint4(u.x, u.y, u.z, __float_as_uint(sg.s.qs[i]));
+    wsp<int2>(ws, sg.o_umeta)[(size_t)b * S + slot] = make_int2(sg.s.key[i], sg.s.type[i]);
+    wsp<int>(ws, sg.o_orig)[(size_t)b * S + slot] = i;
+    wsp<int>(ws, sg.o_slotof)[(size_t)b * Q + i] = slot;
+}
+
+// Padding slots of each column: position of the column's last atom, DUMMY_KEY.
+__global__ void __launch_bounds__(EWB) k_bin_pad(const SegDev* __restrict__ segs, Launch L, char* ws) {
+    const int blk = blockIdx.x;
+    const int p = find_seg(L, blk);
+    const SegDev& sg = segs[p];
+    const int t = (blk - L.pf[p]) * EWB + threadIdx.x;
+    const int ncol = sg.s.ncol, S = sg.s.S;
+    if (t >= L.nb[p] * ncol) return;
+    const int b = t / ncol, col = t - b * ncol;
+    const int n = wsp<const int>(ws, sg.o_colcnt)[(size_t)b * ncol + col];
+    const int pad = (n + 7) & ~7;
+    if (pad == n) return;
+    const int base = wsp<const int>(ws, sg.o_colstart)[(size_t)b * (ncol + 1) + col];
+    uint4* up = wsp<uint4>(ws, sg.o_upos) + (size_t)b * S;
+    int2* um = wsp<int2>(ws, sg.o_umeta) + (size_t)b * S;
+    int* og = wsp<int>(ws, sg.o_orig) + (size_t)b * S;
+    const uint4 last = up[base + n - 1];
+    for (int k = n; k < pad; ++k) {
+        up[base + k] = last;
+        um[base + k] = make_int2(DUMMY_KEY, 0);
+        og[base + k] = -1;
+    }
+}
+
+void run_binning(const SegDev* dsegs, const SegDev* hsegs, const Launch& base, char* ws,
+                 const double* R, int fdsign, double fdh, hipStream_t st) {
+    Launch L = base;
+    // zero histograms (+ max |d|^2 when not binning a displaced configuration)
+    L.pf[0] = 0;
+    for (int p = 0; p < base.nseg; ++p) {
+        const size_t n = (size_t)base.nb[p] * hsegs[p].s.ncol * hsegs[p].s.nzb +
+                         (fdsign == 0 ? hsegs[p].maxN : 0);
+        L.pf[p + 1] = L.pf[p] + (int)((n + EWB - 1) / EWB);
+    }
+    if (L.pf[base.nseg] > 0) hipLaunchKernelGGL(k_zero, dim3(L.pf[base.nseg]), dim3(EWB), 0, st, dsegs, L, ws,
+                                                 fdsign == 0 ? 1 : 0);
+    // atoms
+    Launch La = base;
+    La.pf[0] = 0;
+    for (int p = 0; p < base.nseg; ++p) La.pf[p + 1] = La.pf[p] + base.nb[p] * hsegs[p].bpb;
+    hipLaunchKernelGGL(k_bin_count, dim3(La.pf[base.nseg]), dim3(EWB), 0, st, dsegs, La, ws, R, fdsign, fdh);
+    // columns
+    Launch Lc = base;
+    Lc.pf[0] = 0;
+    for (int p = 0; p < base.nseg; ++p)
+        Lc.pf[p + 1] = Lc.pf[p] + (base.nb[p] * hsegs[p].s.ncol + EWB - 1) / EWB;
+    hipLaunchKernelGGL(k_bin_colscan, dim3(Lc.pf[base.nseg]), dim3(EWB), 0, st, dsegs, Lc, ws);
+    Launch Lb = base;
+    Lb.pf[0] = 0;
+    for (int p = 0; p < base.nseg; ++p) Lb.pf[p + 1] = Lb.pf[p] + base.nb[p];
+    hipLaunchKernelGGL(k_bin_colstart, dim3(Lb.pf[base.nseg]), dim3(CSB), 0, st, dsegs, Lb, ws);
+    hipLaunchKernelGGL(k_bin_scatter, dim3(La.pf[base.nseg]), dim3(EWB), 0, st, dsegs, La, ws);
+    hipLaunchKernelGGL(k_bin_pad, dim3(Lc.pf[base.nseg]), dim3(EWB), 0, st, dsegs, Lc, ws);
+}
+
+}  // namespace mop

@@ -1,0 +1,33 @@
+// Host-side launchers of the kernel files (all asynchronous on `st`).
+#pragma once
+
+#include "mop_internal.h"
+
+namespace mop {
+
+// Bin every pair bead (fdsign: 0 = R, +1 / -1 = R -/+ eps d for the FD term).
+void run_binning(const SegDev* dsegs, const SegDev* hsegs, const Launch& base, char* ws,
+                 const double* R, int fdsign, double fdh, hipStream_t st);
+
+// Pair kernels.  mode 0: forces into f32 (outsel 0), hv32 (outsel 1) or f32m (outsel 2);
+// energy_bead: -1 none, -2 every bead, b >= 0 that bead only.  mode 1: H v from vs into hv32.
+void run_pair(const SegDev* dsegs, const SegDev* hsegs, const Launch& base, char* ws, int mode,
+              int outsel, int energy_bead, int waves, hipStream_t st);
+
+// FP64 path kernels.
+void run_resid(const SegDev* dsegs, const SegDev* hsegs, const Launch& base, const CallPtrs& cp,
+               hipStream_t st);
+void run_assemble(const SegDev* dsegs, const SegDev* hsegs, const Launch& base, const CallPtrs& cp,
+                  int fd, hipStream_t st);
+void run_reduce_veff(const SegDev* dsegs, const SegDev* hsegs, const Launch& base,
+                     const CallPtrs& cp, hipStream_t st);
+// bead_forces / bead_hvp finishing kernels.
+void run_finalize_forces(const SegDev* dsegs, const SegDev* hsegs, const Launch& base,
+                         const CallPtrs& cp, hipStream_t st);
+void run_prep_v(const SegDev* dsegs, const SegDev* hsegs, const Launch& base, const CallPtrs& cp,
+                hipStream_t st);
+void run_finalize_hvp(const SegDev* dsegs, const SegDev* hsegs, const Launch& base,
+                      const CallPtrs& cp, hipStream_t st);
+void run_status_clear(int* status, hipStream_t st);
+
+}  // namespace mop

@@ -1,0 +1,687 @@
+// Host runtime behind include/mop.h: validation, device tables, plan geometry,
+// workspace layout and the call sequences of every entry point.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/mop.h"
+#include "launch.h"
+#include "mop_internal.h"
+
+using namespace mop;
+
+namespace {
+
+constexpr double F_ELEC = 138.935458;  // kJ mol^-1 nm e^-2
+constexpr double SEARCH_MARGIN = 1.0e-4;  // nm added to the cutoff for neighbour pruning
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace
+
+struct mop_ctx_s {
+    int device;
+    hipStream_t stream;
+};
+
+struct mop_system_s {
+    mop_ctx ctx;
+    SysDev dev;           // device pointers; geometry fields filled per plan
+    double box[3];
+    double rc;
+    std::vector<void*> allocs;
+};
+
+struct mop_plan_s {
+    mop_system sys;
+    int max_beads;
+    int waves;
+    SegDev hseg;          // single-path layout (capacity max_beads)
+    SegDev* dseg;
+    size_t ws_bytes;
+};
+
+struct mop_batch_s {
+    mop_ctx ctx;
+    int P;
+    int waves;
+    std::vector<int> N;
+    std::vector<SegDev> hsegs;
+    SegDev* dsegs;
+    size_t ws_bytes;
+};
+
+// ---------------------------------------------------------------------------------
+// validation and exclusion keys
+// ---------------------------------------------------------------------------------
+
+static int check_desc(const mop_system_desc* d) {
+    if (!d || d->Q < 1 || !d->mass || !d->charge || !d->type || !d->sigma || !d->epsilon)
+        return MOP_EINVAL;
+    if (d->ntypes < 1) return MOP_ETYPE;
+    if (d->ntypes > MAXTYPES) return MOP_ETYPE;
+    if (d->nbonds < 0 || (d->nbonds > 0 && (!d->bond_ij || !d->bond_r0 || !d->bond_k)))
+        return MOP_EINVAL;
+    if ((d->excl_mol == nullptr) != (d->excl_pos == nullptr)) return MOP_EINVAL;
+    for (int a = 0; a < 3; ++a)
+        if (!(d->box[a] > 0.0) || !std::isfinite(d->box[a])) return MOP_EINVAL;
+    if (!(d->dt > 0.0) || !(d->nu > 0.0) || !(d->eps_r > 0.0) || !std::isfinite(d->eps_rf))
+        return MOP_EINVAL;
+    const double bmin = std::min(d->box[0], std::min(d->box[1], d->box[2]));
+    if (!(d->r_cut > 0.0) || !(d->r_cut + SEARCH_MARGIN < 0.5 * bmin)) return MOP_ECUTOFF;
+    for (int i = 0; i < d->Q; ++i) {
+        if (!(d->mass[i] > 0.0) || !std::isfinite(d->charge[i])) return MOP_EINVAL;
+        if (d->type[i] < 0 || d->type[i] >= d->ntypes) return MOP_ETYPE;
+    }
+    for (int t = 0; t < d->ntypes; ++t)
+        if (!(d->sigma[t] >= 0.0) || !(d->epsilon[t] >= 0.0)) return MOP_EINVAL;
+    for (int b = 0; b < d->nbonds; ++b) {
+        const int i = d->bond_ij[2 * b], j = d->bond_ij[2 * b + 1];
+        if (i < 0 || j < 0 || i >= d->Q || j >= d->Q || i == j) return MOP_EINVAL;
+        if (!(d->bond_r0[b] > 0.0) || !(d->bond_k[b] >= 0.0)) return MOP_EINVAL;
+    }
+    if (d->excl_mol)
+        for (int i = 0; i < d->Q; ++i)
+            if (d->excl_mol[i] < 0 || d->excl_pos[i] < 0) return MOP_EINVAL;
+    return MOP_OK;
+}
+
+// Exclusion key per atom: molecule id * 2^sh + position along the chain, with
+// 2^sh >= max position + 3 so that |key_i - key_j| <= 2 only within a molecule.
+// Without explicit molecules the bonds must form linear chains (degree <= 2, no cycles),
+// which are walked from one end.
+static int make_keys(const mop_system_desc* d, std::vector<int>& key) {
+    const int Q = d->Q;
+    std::vector<int> mol(Q), pos(Q);
+    if (d->excl_mol) {
+        for (int i = 0; i < Q; ++i) {
+            mol[i] = d->excl_mol[i];
+            pos[i] = d->excl_pos[i];
+        }
+    } else {
+        std::vector<int> deg(Q, 0), nb0(Q, -1), nb1(Q, -1);
+        for (int b = 0; b < d->nbonds; ++b) {
+            const int i = d->bond_ij[2 * b], j = d->bond_ij[2 * b + 1];
+            for (int k = 0; k < 2; ++k) {
+                const int a = k ? j : i, o = k ? i : j;
+                if (deg[a] >= 2) return MOP_ETOPOLOGY;
+                if (deg[a] == 1 && nb0[a] == o) return MOP_ETOPOLOGY;  // duplicate bond
+                (deg[a] == 0 ? nb0[a] : nb1[a]) = o;
+                ++deg[a];
+            }
+        }
+        std::vector<char> seen(Q, 0);
+        int m = 0;
+        for (int s = 0; s < Q; ++s) {
+            if (seen[s] || deg[s] == 2) continue;  // start at chain ends and lone atoms
+            int prev = -1, cur = s, p = 0;
+            while (cur >= 0) {
+                seen[cur] = 1;
+                mol[cur] = m;
+                pos[cur] = p++;
+                const int nxt = nb0[cur] != prev ? nb0[cur] : nb1[cur];
+                prev = cur;
+                cur = (nxt >= 0 && !seen[nxt]) ? nxt : -1;
+            }
+            ++m;
+        }
+        for (int i = 0; i < Q; ++i)
+            if (!seen[i]) return MOP_ETOPOLOGY;  // an atom on a ring
+    }
+    int maxpos = 0, maxmol = 0;
+    for (int i = 0; i < Q; ++i) {
+        maxpos = std::max(maxpos, pos[i]);
+        maxmol = std::max(maxmol, mol[i]);
+    }
+    int sh = 0;
+    while ((1 << sh) < maxpos + 3) ++sh;
+    if ((double)maxmol * (double)(1 << sh) + maxpos >= 2147483000.0) return MOP_ETOPOLOGY;
+    key.resize(Q);
+    for (int i = 0; i < Q; ++i) key[i] = mol[i] * (1 << sh) + pos[i];
+    return MOP_OK;
+}
+
+template <class T>
+static int upload(mop_system sys, const T* h, size_t n, const T** out) {
+    void* p = nullptr;
+    const size_t bytes = std::max<size_t>(n, 1) * sizeof(T);
+    if (hipMalloc(&p, bytes) != hipSuccess) return MOP_ENOMEM;
+    sys->allocs.push_back(p);
+    if (n && hipMemcpy(p, h, n * sizeof(T), hipMemcpyHostToDevice) != hipSuccess) return MOP_EHIP;
+    *out = static_cast<const T*>(p);
+    return MOP_OK;
+}
+
+// ---------------------------------------------------------------------------------
+// workspace layout
+// ---------------------------------------------------------------------------------
+
+// Offsets of one path's arrays starting at byte `base`; returns the end offset.
+static size_t layout(SegDev& sg, int maxb, int maxN, size_t base) {
+    const SysDev& s = sg.s;
+    const size_t Q = s.Q, S = s.S, nc = s.ncol, nz = s.nzb, B = maxb;
+    size_t o = align256(base);
+    auto take = [&](size_t& off, size_t bytes) {
+        off = o;
+        o = align256(o + bytes);
+    };
+    take(sg.o_upos, B * S * 16);
+    take(sg.o_umeta, B * S * 8);
+    take(sg.o_orig, B * S * 4);
+    take(sg.o_slotof, B * Q * 4);
+    take(sg.o_atomu, B * Q * 16);
+    take(sg.o_rank, B * Q * 4);
+    take(sg.o_bincnt, B * nc * nz * 4);
+    take(sg.o_binoff, B * nc * (nz + 1) * 4);
+    take(sg.o_colcnt, B * nc * 4);
+    take(sg.o_colstart, B * (nc + 1) * 4);
+    take(sg.o_vs, B * S * 16);
+    take(sg.o_f32, B * Q * 16);
+    take(sg.o_f32m, B * Q * 16);
+    take(sg.o_hv32, B * Q * 16);
+    take(sg.o_epart, B * (size_t)s.cpb * 8);
+    take(sg.o_d64, (size_t)std::max(maxN - 1, 1) * Q * 24);
+    take(sg.o_rpart, (size_t)std::max(maxN, maxb) * sg.bpb * 16);
+    take(sg.o_dmax, (size_t)std::max(maxN, 1) * 8);
+    take(sg.o_eres, 4 * 8);
+    sg.maxb = maxb;
+    sg.maxN = maxN;
+    return o;
+}
+
+static SysDev plan_geometry(const mop_system_s* sys, const mop_plan_opts* opts) {
+    SysDev s = sys->dev;
+    const double cwt = (opts && opts->col_width > 0.0) ? opts->col_width : 0.5;
+    const double zbt = (opts && opts->zbin > 0.0) ? opts->zbin : 0.1;
+    const double* L = sys->box;
+    s.ncx = std::max(1, (int)std::floor(L[0] / cwt));
+    s.ncy = std::max(1, (int)std::floor(L[1] / cwt));
+    s.nzb = std::max(1, (int)std::floor(L[2] / zbt));
+    s.ncol = s.ncx * s.ncy;
+    const double cwx = L[0] / s.ncx, cwy = L[1] / s.ncy;
+    const double rcs = sys->rc + SEARCH_MARGIN;
+    s.rx = (int)std::ceil(rcs / cwx);
+    s.ry = (int)std::ceil(rcs / cwy);
+    s.wx = 2 * s.rx + 1;
+    s.wy = 2 * s.ry + 1;
+    s.allx = s.wx >= s.ncx;
+    s.ally = s.wy >= s.ncy;
+    if (s.allx) s.wx = s.ncx;
+    if (s.ally) s.wy = s.ncy;
+    s.S = ((s.Q + 7 * s.ncol) + 7) & ~7;
+    s.cpb = s.S / CLUSTER;
+    for (int a = 0; a < 3; ++a) {
+        s.L[a] = L[a];
+        s.Lf[a] = (float)L[a];
+        s.sc[a] = (float)(L[a] / 4294967296.0);
+    }
+    s.cw[0] = (float)cwx;
+    s.cw[1] = (float)cwy;
+    s.rcs = (float)rcs;
+    s.rcs2 = (float)(rcs * rcs);
+    return s;
+}
+
+static void base_seg(SegDev& sg, const SysDev& s) {
+    std::memset(&sg, 0, sizeof(sg));
+    sg.s = s;
+    sg.bpb = (s.Q + EWB - 1) / EWB;
+}
+
+// ---------------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------------
+
+extern "C" {
+
+const char* mop_strerror(int code) {
+    switch (code) {
+        case MOP_OK: return "ok";
+        case MOP_EINVAL: return "invalid argument";
+        case MOP_ECUTOFF: return "cutoff must be positive and below half the smallest box length";
+        case MOP_ETYPE: return "atom type out of range or too many types (max 16)";
+        case MOP_EHIP: return "HIP runtime error (no usable device?)";
+        case MOP_ENOMEM: return "device allocation failed";
+        case MOP_ETOPOLOGY: return "bonds do not form linear chains; give excl_mol/excl_pos";
+        case MOP_ESIZE: return "more beads or paths than the plan or batch was created for";
+        default: return "unknown error";
+    }
+}
+
+int mop_system_check(const mop_system_desc* desc) {
+    int rc = check_desc(desc);
+    if (rc) return rc;
+    std::vector<int> key;
+    return make_keys(desc, key);
+}
+
+int mop_ctx_create(int device, void* hip_stream, mop_ctx* out) {
+    if (!out) return MOP_EINVAL;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return MOP_EHIP;
+    if (hipSetDevice(device) != hipSuccess) return MOP_EHIP;
+    mop_ctx c = new (std::nothrow) mop_ctx_s;
+    if (!c) return MOP_ENOMEM;
+    c->device = device;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    *out = c;
+    return MOP_OK;
+}
+
+int mop_ctx_set_stream(mop_ctx ctx, void* hip_stream) {
+    if (!ctx) return MOP_EINVAL;
+    ctx->stream = static_cast<hipStream_t>(hip_stream);
+    return MOP_OK;
+}
+
+void mop_ctx_destroy(mop_ctx ctx) { delete ctx; }
+
+int mop_system_create(mop_ctx ctx, const mop_system_desc* d, mop_system* out) {
+    if (!ctx || !out) return MOP_EINVAL;
+    *out = nullptr;
+    int err = check_desc(d);
+    if (err) return err;
+    std::vector<int> key;
+    err = make_keys(d, key);
+    if (err) return err;
+    if (hipSetDevice(ctx->device) != hipSuccess) return MOP_EHIP;
+    mop_system sys = new (std::nothrow) mop_system_s;
+    if (!sys) return MOP_ENOMEM;
+    sys->ctx = ctx;
+    std::memset(&sys->dev, 0, sizeof(SysDev));
+    const int Q = d->Q, nt = d->ntypes;
+    for (int a = 0; a < 3; ++a) sys->box[a] = d->box[a];
+    sys->rc = d->r_cut;
+    SysDev& s = sys->dev;
+    s.Q = Q;
+    s.nt = nt;
+    const double rc = d->r_cut;
+    const double fq = F_ELEC / d->eps_r;
+    const double krf = (d->eps_rf - d->eps_r) / ((2.0 * d->eps_rf + d->eps_r) * rc * rc * rc);
+    const double crf = 1.0 / rc + krf * rc * rc;
+    const double crf1 = 1.0 / (rc * rc) - 2.0 * krf * rc;
+    s.rc2 = (float)(rc * rc);
+    s.krf = (float)krf;
+    s.krf2 = (float)(2.0 * krf);
+    s.crf = (float)crf;
+    s.crf1 = (float)crf1;
+    s.e0rf = (float)(-rc * crf1);
+    // per atom
+    std::vector<float> qs(Q);
+    std::vector<int> typ(Q);
+    std::vector<double> c(Q), K(Q);
+    const double sq = std::sqrt(fq);
+    for (int i = 0; i < Q; ++i) {
+        qs[i] = (float)(d->charge[i] * sq);
+        typ[i] = d->type[i];
+        c[i] = d->dt / (d->mass[i] * d->nu);
+        K[i] = d->mass[i] * d->nu / (2.0 * d->dt);
+    }
+    // type-pair tables (Lorentz-Berthelot), shifted-force constants at r_cut
+    std::vector<float4> tab(nt * nt), tab2(nt * nt);
+    for (int a = 0; a < nt; ++a)
+        for (int b = 0; b < nt; ++b) {
+            const double sg = 0.5 * (d->sigma[a] + d->sigma[b]);
+            const double ep = std::sqrt(d->epsilon[a] * d->epsilon[b]);
+            const double s6 = std::pow(sg, 6.0);
+            const double c6 = 4.0 * ep * s6, c12 = 4.0 * ep * s6 * s6;
+            const double ir = 1.0 / rc, ir6 = std::pow(ir, 6.0);
+            const double phic = c12 * ir6 * ir6 - c6 * ir6;
+            const double dphic = (-12.0 * c12 * ir6 * ir6 + 6.0 * c6 * ir6) * ir;
+            const double csf = -dphic;
+            const double e0 = -phic - rc * csf;
+            tab[a * nt + b] = make_float4((float)(-12.0 * c12), (float)(6.0 * c6), (float)csf, (float)e0);
+            tab2[a * nt + b] = make_float4((float)(168.0 * c12), (float)(-48.0 * c6), (float)c12, (float)c6);
+        }
+    // bond CSR (each bond listed for both atoms)
+    std::vector<int> bstart(Q + 1, 0), bpart(2 * (size_t)d->nbonds);
+    std::vector<double> br0(2 * (size_t)d->nbonds), bk(2 * (size_t)d->nbonds);
+    for (int b = 0; b < d->nbonds; ++b) {
+        ++bstart[d->bond_ij[2 * b] + 1];
+        ++bstart[d->bond_ij[2 * b + 1] + 1];
+    }
+    for (int i = 0; i < Q; ++i) bstart[i + 1] += bstart[i];
+    {
+        std::vector<int> fill(bstart.begin(), bstart.end() - 1);
+        for (int b = 0; b < d->nbonds; ++b) {
+            const int i = d->bond_ij[2 * b], j = d->bond_ij[2 * b + 1];
+            int k = fill[i]++;
+            bpart[k] = j;
+            br0[k] = d->bond_r0[b];
+            bk[k] = d->bond_k[b];
+            k = fill[j]++;
+            bpart[k] = i;
+            br0[k] = d->bond_r0[b];
+            bk[k] = d->bond_k[b];
+        }
+    }
+    s.nbond_entries = 2 * d->nbonds;
+    int e = 0;
+    if (!e) e = upload(sys, qs.data(), Q, &s.qs);
+    if (!e) e = upload(sys, key.data(), Q, &s.key);
+    if (!e) e = upload(sys, typ.data(), Q, &s.type);
+    if (!e) e = upload(sys, c.data(), Q, &s.c);
+    if (!e) e = upload(sys, K.data(), Q, &s.K);
+    if (!e) e = upload(sys, bstart.data(), Q + 1, &s.bstart);
+    if (!e) e = upload(sys, bpart.data(), bpart.size(), &s.bpart);
+    if (!e) e = upload(sys, br0.data(), br0.size(), &s.br0);
+    if (!e) e = upload(sys, bk.data(), bk.size(), &s.bk);
+    if (!e) e = upload(sys, tab.data(), tab.size(), &s.tab);
+    if (!e) e = upload(sys, tab2.data(), tab2.size(), &s.tab2);
+    if (e) {
+        mop_system_destroy(sys);
+        return e;
+    }
+    *out = sys;
+    return MOP_OK;
+}
+
+void mop_system_destroy(mop_system sys) {
+    if (!sys) return;
+    for (void* p : sys->allocs) (void)hipFree(p);
+    delete sys;
+}
+
+int mop_plan_create(mop_system sys, int32_t max_beads, const mop_plan_opts* opts, mop_plan* out) {
+    if (!sys || !out || max_beads < 1) return MOP_EINVAL;
+    *out = nullptr;
+    int waves = opts && opts->waves ? opts->waves : 4;
+    if (waves != 1 && waves != 2 && waves != 4 && waves != 8) return MOP_EINVAL;
+    if (opts && (opts->col_width < 0.0 || opts->zbin < 0.0)) return MOP_EINVAL;
+    if (hipSetDevice(sys->ctx->device) != hipSuccess) return MOP_EHIP;
+    mop_plan pl = new (std::nothrow) mop_plan_s;
+    if (!pl) return MOP_ENOMEM;
+    pl->sys = sys;
+    pl->max_beads = max_beads;
+    pl->waves = waves;
+    base_seg(pl->hseg, plan_geometry(sys, opts));
+    pl->hseg.roff = 0;
+    pl->hseg.vidx = 0;
+    pl->ws_bytes = layout(pl->hseg, max_beads, max_beads, 256);
+    pl->dseg = nullptr;
+    if (hipMalloc(&pl->dseg, sizeof(SegDev)) != hipSuccess) {
+        delete pl;
+        return MOP_ENOMEM;
+    }
+    if (hipMemcpy(pl->dseg, &pl->hseg, sizeof(SegDev), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(pl->dseg);
+        delete pl;
+        return MOP_EHIP;
+    }
+    *out = pl;
+    return MOP_OK;
+}
+
+void mop_plan_destroy(mop_plan plan) {
+    if (!plan) return;
+    if (plan->dseg) (void)hipFree(plan->dseg);
+    delete plan;
+}
+
+int mop_workspace_size(mop_plan plan, size_t* bytes) {
+    if (!plan || !bytes) return MOP_EINVAL;
+    *bytes = plan->ws_bytes;
+    return MOP_OK;
+}
+
+int mop_plan_info(mop_plan plan, int32_t* ncx, int32_t* ncy, int32_t* nzb, int32_t* slots) {
+    if (!plan) return MOP_EINVAL;
+    if (ncx) *ncx = plan->hseg.s.ncx;
+    if (ncy) *ncy = plan->hseg.s.ncy;
+    if (nzb) *nzb = plan->hseg.s.nzb;
+    if (slots) *slots = plan->hseg.s.S;
+    return MOP_OK;
+}
+
+static Launch one_path(int N, int nb) {
+    Launch L;
+    std::memset(&L, 0, sizeof(L));
+    L.nseg = 1;
+    L.N[0] = N;
+    L.nb[0] = nb;
+    return L;
+}
+
+static CallPtrs call_ptrs(void* ws) {
+    CallPtrs cp;
+    std::memset(&cp, 0, sizeof(cp));
+    cp.ws = static_cast<char*>(ws);
+    cp.status = static_cast<int*>(ws);
+    return cp;
+}
+
+static int finish(mop_ctx ctx) {
+    (void)ctx;
+    return hipGetLastError() == hipSuccess ? MOP_OK : MOP_EHIP;
+}
+
+int bead_forces(mop_plan plan, const double* R, int32_t B, float* F, double* U, void* ws) {
+    if (!plan || !R || !F || !ws) return MOP_EINVAL;
+    if (B < 1) return MOP_EINVAL;
+    if (B > plan->max_beads) return MOP_ESIZE;
+    hipStream_t st = plan->sys->ctx->stream;
+    CallPtrs cp = call_ptrs(ws);
+    cp.R = R;
+    cp.Fout = F;
+    cp.Uout = U;
+    const Launch L = one_path(B, B);
+    run_binning(plan->dseg, &plan->hseg, L, cp.ws, R, 0, 0.0, st);
+    run_pair(plan->dseg, &plan->hseg, L, cp.ws, 0, 0, U ? -2 : -1, plan->waves, st);
+    run_finalize_forces(plan->dseg, &plan->hseg, L, cp, st);
+    return finish(plan->sys->ctx);
+}
+
+int bead_hvp(mop_plan plan, const double* R, const double* V, int32_t B, float* HV, void* ws) {
+    if (!plan || !R || !V || !HV || !ws) return MOP_EINVAL;
+    if (B < 1) return MOP_EINVAL;
+    if (B > plan->max_beads) return MOP_ESIZE;
+    hipStream_t st = plan->sys->ctx->stream;
+    CallPtrs cp = call_ptrs(ws);
+    cp.R = R;
+    cp.V = V;
+    cp.Fout = HV;
+    const Launch L = one_path(B, B);
+    run_binning(plan->dseg, &plan->hseg, L, cp.ws, R, 0, 0.0, st);
+    run_prep_v(plan->dseg, &plan->hseg, L, cp, st);
+    run_pair(plan->dseg, &plan->hseg, L, cp.ws, 1, 0, -1, plan->waves, st);
+    run_finalize_hvp(plan->dseg, &plan->hseg, L, cp, st);
+    return finish(plan->sys->ctx);
+}
+
+// The phases of V_eff and its gradient over every path of `base`.  ev, when given,
+// receives an event after each phase (MOP_NPHASES + 1 events, ev[0] at the start).
+static void path_sequence(const SegDev* dsegs, const SegDev* hsegs, const Launch& base,
+                          const CallPtrs& cp, bool grad, int mode, int waves, hipStream_t st,
+                          hipEvent_t* ev = nullptr) {
+    auto mark = [&](int k) {
+        if (ev) (void)hipEventRecord(ev[k], st);
+    };
+    mark(0);
+    // forces of beads 1..N-1 (bead 1 alone for N = 1), energy of bead 1
+    run_binning(dsegs, hsegs, base, cp.ws, cp.R, 0, 0.0, st);
+    mark(1);
+    run_pair(dsegs, hsegs, base, cp.ws, 0, 0, 0, waves, st);
+    mark(2);
+    run_resid(dsegs, hsegs, base, cp, st);
+    mark(3);
+    if (grad) {
+        Launch Lh = base;
+        bool any = false;
+        for (int p = 0; p < base.nseg; ++p) {
+            Lh.nb[p] = base.N[p] - 1;
+            any = any || Lh.nb[p] > 0;
+        }
+        if (any && mode == 0) run_pair(dsegs, hsegs, Lh, cp.ws, 1, 0, -1, waves, st);
+        mark(4);
+        if (any && mode == 1) {
+            run_binning(dsegs, hsegs, Lh, cp.ws, cp.R, +1, cp.fd_h, st);
+            run_pair(dsegs, hsegs, Lh, cp.ws, 0, 1, -1, waves, st);
+            run_binning(dsegs, hsegs, Lh, cp.ws, cp.R, -1, cp.fd_h, st);
+            run_pair(dsegs, hsegs, Lh, cp.ws, 0, 2, -1, waves, st);
+        }
+        mark(5);
+        run_assemble(dsegs, hsegs, base, cp, mode, st);
+    } else {
+        mark(4);
+        mark(5);
+    }
+    run_reduce_veff(dsegs, hsegs, base, cp, st);
+    mark(6);
+}
+
+int veff_energy(mop_plan plan, const double* R, int32_t N, double* veff, double* u1,
+                double* espring, void* ws) {
+    if (!plan || !R || !ws) return MOP_EINVAL;
+    if (N < 1) return MOP_EINVAL;
+    if (N > plan->max_beads) return MOP_ESIZE;
+    CallPtrs cp = call_ptrs(ws);
+    cp.R = R;
+    cp.veff = veff;
+    cp.u1 = u1;
+    cp.espring = espring;
+    const Launch L = one_path(N, N > 1 ? N - 1 : 1);
+    path_sequence(plan->dseg, &plan->hseg, L, cp, false, 0, plan->waves, plan->sys->ctx->stream);
+    return finish(plan->sys->ctx);
+}
+
+int veff_grad(mop_plan plan, const double* R, int32_t N, double* G, double* veff, int32_t mode,
+              double fd_h, void* ws) {
+    if (!plan || !R || !G || !ws) return MOP_EINVAL;
+    if (N < 1 || (mode != 0 && mode != 1)) return MOP_EINVAL;
+    if (mode == 1 && !(fd_h > 0.0)) return MOP_EINVAL;
+    if (N > plan->max_beads) return MOP_ESIZE;
+    CallPtrs cp = call_ptrs(ws);
+    cp.R = R;
+    cp.G = G;
+    cp.veff = veff;
+    cp.fd_h = fd_h;
+    const Launch L = one_path(N, N > 1 ? N - 1 : 1);
+    path_sequence(plan->dseg, &plan->hseg, L, cp, true, mode, plan->waves, plan->sys->ctx->stream);
+    return finish(plan->sys->ctx);
+}
+
+int veff_grad_timed(mop_plan plan, const double* R, int32_t N, double* G, double* veff,
+                    int32_t mode, double fd_h, void* ws, float* phase_ms) {
+    if (!plan || !R || !G || !ws || !phase_ms) return MOP_EINVAL;
+    if (N < 1 || (mode != 0 && mode != 1)) return MOP_EINVAL;
+    if (mode == 1 && !(fd_h > 0.0)) return MOP_EINVAL;
+    if (N > plan->max_beads) return MOP_ESIZE;
+    hipStream_t st = plan->sys->ctx->stream;
+    hipEvent_t ev[MOP_NPHASES + 1];
+    for (int k = 0; k <= MOP_NPHASES; ++k)
+        if (hipEventCreate(&ev[k]) != hipSuccess) return MOP_EHIP;
+    CallPtrs cp = call_ptrs(ws);
+    cp.R = R;
+    cp.G = G;
+    cp.veff = veff;
+    cp.fd_h = fd_h;
+    const Launch L = one_path(N, N > 1 ? N - 1 : 1);
+    path_sequence(plan->dseg, &plan->hseg, L, cp, true, mode, plan->waves, st, ev);
+    int rc = finish(plan->sys->ctx);
+    if (hipEventSynchronize(ev[MOP_NPHASES]) != hipSuccess) rc = MOP_EHIP;
+    for (int k = 0; k < MOP_NPHASES; ++k) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, ev[k], ev[k + 1]) != hipSuccess) rc = MOP_EHIP;
+        phase_ms[k] = ms;
+    }
+    for (int k = 0; k <= MOP_NPHASES; ++k) (void)hipEventDestroy(ev[k]);
+    return rc;
+}
+
+int mop_batch_create(int32_t P, const mop_plan* plans, const int32_t* N, mop_batch* out) {
+    if (!out || !plans || !N || P < 1) return MOP_EINVAL;
+    *out = nullptr;
+    if (P > MAXSEG) return MOP_ESIZE;
+    mop_ctx ctx = plans[0] ? plans[0]->sys->ctx : nullptr;
+    if (!ctx) return MOP_EINVAL;
+    for (int p = 0; p < P; ++p) {
+        if (!plans[p] || plans[p]->sys->ctx != ctx || N[p] < 1) return MOP_EINVAL;
+        if (N[p] > plans[p]->max_beads) return MOP_ESIZE;
+    }
+    if (hipSetDevice(ctx->device) != hipSuccess) return MOP_EHIP;
+    mop_batch bt = new (std::nothrow) mop_batch_s;
+    if (!bt) return MOP_ENOMEM;
+    bt->ctx = ctx;
+    bt->P = P;
+    bt->waves = plans[0]->waves;
+    bt->N.assign(N, N + P);
+    bt->hsegs.resize(P);
+    size_t off = 256;
+    long long roff = 0;
+    for (int p = 0; p < P; ++p) {
+        SegDev& sg = bt->hsegs[p];
+        base_seg(sg, plans[p]->hseg.s);
+        sg.roff = roff;
+        sg.vidx = p;
+        off = layout(sg, std::max(N[p] - 1, 1), N[p], off);
+        roff += (long long)N[p] * sg.s.Q * 3;
+    }
+    bt->ws_bytes = off;
+    bt->dsegs = nullptr;
+    if (hipMalloc(&bt->dsegs, sizeof(SegDev) * P) != hipSuccess) {
+        delete bt;
+        return MOP_ENOMEM;
+    }
+    if (hipMemcpy(bt->dsegs, bt->hsegs.data(), sizeof(SegDev) * P, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(bt->dsegs);
+        delete bt;
+        return MOP_EHIP;
+    }
+    *out = bt;
+    return MOP_OK;
+}
+
+void mop_batch_destroy(mop_batch batch) {
+    if (!batch) return;
+    if (batch->dsegs) (void)hipFree(batch->dsegs);
+    delete batch;
+}
+
+int mop_batch_workspace_size(mop_batch batch, size_t* bytes) {
+    if (!batch || !bytes) return MOP_EINVAL;
+    *bytes = batch->ws_bytes;
+    return MOP_OK;
+}
+
+int mop_batch_veff_grad(mop_batch batch, const double* R, double* G, double* veff, int32_t mode,
+                        double fd_h, void* ws) {
+    if (!batch || !R || !G || !ws) return MOP_EINVAL;
+    if ((mode != 0 && mode != 1) || (mode == 1 && !(fd_h > 0.0))) return MOP_EINVAL;
+    CallPtrs cp = call_ptrs(ws);
+    cp.R = R;
+    cp.G = G;
+    cp.veff = veff;
+    cp.fd_h = fd_h;
+    Launch L;
+    std::memset(&L, 0, sizeof(L));
+    L.nseg = batch->P;
+    for (int p = 0; p < batch->P; ++p) {
+        L.N[p] = batch->N[p];
+        L.nb[p] = batch->N[p] > 1 ? batch->N[p] - 1 : 1;
+    }
+    path_sequence(batch->dsegs, batch->hsegs.data(), L, cp, true, mode, batch->waves, batch->ctx->stream);
+    return finish(batch->ctx);
+}
+
+int mop_status(mop_plan plan, const void* ws, int32_t* device_status) {
+    if (!plan || !ws || !device_status) return MOP_EINVAL;
+    if (hipStreamSynchronize(plan->sys->ctx->stream) != hipSuccess) return MOP_EHIP;
+    int v = 0;
+    if (hipMemcpy(&v, ws, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return MOP_EHIP;
+    *device_status = v;
+    return MOP_OK;
+}
+
+int mop_status_clear(mop_plan plan, void* ws) {
+    if (!plan || !ws) return MOP_EINVAL;
+    run_status_clear(static_cast<int*>(ws), plan->sys->ctx->stream);
+    return finish(plan->sys->ctx);
+}
+
+}  // extern "C"

@@ -1,0 +1,104 @@
+// Internal layout shared by the host runtime (mop_api.cpp) and the HIP kernels.
+//
+// Data layout in HBM, per bead with pair work (a "pair bead"):
+//   atoms are binned into nc_x * nc_y columns of the x-y plane (column width about
+//   0.5 nm) and, inside each column, counting-sorted by z bin.  Each column's slot
+//   range is padded to a multiple of 8 so that it splits into 8-atom clusters; padding
+//   slots carry DUMMY_KEY.  Sorted arrays (structure of arrays, one entry per slot):
+//     upos  uint4  {x, y, z fixed point (box = 2^32 units), charge bits (float)}
+//     umeta int2   {exclusion key, LJ type}
+//     orig  int    atom index of the slot (-1 for padding)
+//     vs    float4 the vector of a Hessian-vector product, slot order
+//   Per atom (original order): slotof, pair force / pair HVP outputs (float4).
+// Per path: FP64 residuals d^n [(N-1)][Q][3], reduction partials, per-bead max |d|^2.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cstddef>
+#include <cstdint>
+
+namespace mop {
+
+constexpr int MAXSEG = 32;        // paths per launch
+constexpr int CLUSTER = 8;        // atoms per cluster
+constexpr int RING = 128;         // j-atom ring per wave (power of two, >= 2*64)
+constexpr int CLIST = 256;        // candidate-cluster list per wave
+constexpr int MAXTYPES = 16;      // LJ types
+constexpr int EWB = 256;          // block size of the elementwise kernels
+constexpr int32_t DUMMY_KEY = INT32_MIN;
+
+// Status bits (mirrors MOP_DEV_* of the public header).
+constexpr int ST_NONFINITE = 1;
+constexpr int ST_CAPACITY = 2;
+
+struct SysDev {
+    int Q, ncx, ncy, ncol, nzb, nt;
+    int S;            // slots per bead (multiple of 8)
+    int cpb;          // clusters per bead (S / 8)
+    int allx, ally;   // 1: the column stencil spans every column along that axis
+    int rx, ry;       // stencil half widths (columns) when not spanning
+    int wx, wy;       // stencil widths (columns)
+    int nbond_entries;
+    double L[3];
+    float sc[3];      // nm per fixed-point unit: L / 2^32
+    float Lf[3];
+    float cw[2];      // column widths (nm)
+    float rc2;        // cutoff^2
+    float rcs;        // neighbour-search radius (cutoff + margin)
+    float rcs2;
+    float krf2;       // 2 k_rf
+    float krf, crf;   // reaction-field constants (energy)
+    float crf1;       // 1/rc^2 - 2 k_rf rc: -phi_RF'(rc) / (q_i q_j)
+    float e0rf;       // -rc * crf1
+    const float* qs;      // [Q] charge * sqrt(f / eps_r)
+    const int* key;       // [Q] exclusion key: same molecule and |key_i - key_j| <= 2
+    const int* type;      // [Q]
+    const double* c;      // [Q] dt / (m nu)
+    const double* K;      // [Q] m nu / (2 dt)
+    const int* bstart;    // [Q + 1] bond CSR (each bond listed for both atoms)
+    const int* bpart;     // partner atom
+    const double* br0;
+    const double* bk;
+    const float4* tab;    // [nt*nt] {a12 = -12 c12, a6 = 6 c6, csf = -phi_LJ'(rc), e0lj}
+    const float4* tab2;   // [nt*nt] {b12 = 168 c12, b6 = -48 c6, c12, c6}
+};
+
+// One path (segment) of a launch.  Byte offsets are relative to the workspace base.
+struct SegDev {
+    SysDev s;
+    int maxb;             // pair-bead capacity of the layout
+    int maxN;             // bead capacity of the path arrays
+    long long roff;       // element offset of this path's bead 0 in R / G / V / F
+    int vidx;             // index of this path's scalar outputs
+    int bpb;              // elementwise blocks per bead: ceil(Q / EWB)
+    size_t o_upos, o_umeta, o_orig, o_slotof, o_atomu, o_rank, o_bincnt, o_binoff,
+        o_colcnt, o_colstart, o_vs, o_f32, o_f32m, o_hv32, o_epart, o_d64, o_rpart,
+        o_dmax, o_eres;
+};
+
+// Per-launch description, passed by value.
+struct Launch {
+    int nseg;
+    int pf[MAXSEG + 1];   // block prefix per segment
+    int N[MAXSEG];        // beads of each path in this call
+    int nb[MAXSEG];       // pair beads of each path in this call
+};
+
+// Pointers of one call (device).
+struct CallPtrs {
+    const double* R;      // bead coordinates, packed paths
+    const double* V;      // HVP input (bead_hvp) or null
+    double* G;            // gradient out
+    float* Fout;          // bead_forces / bead_hvp out (float)
+    double* Uout;         // bead_forces energies / scalar outputs
+    double* veff;         // [P] or null
+    double* u1;
+    double* espring;
+    char* ws;
+    int* status;
+    double fd_h;
+};
+
+}  // namespace mop

@@ -1,0 +1,99 @@
+"""C-ABI contract tests that need no GPU: the library loads, exports every function
+include/mop.h declares, and rejects bad system descriptions on the host."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mop.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][\w\s\*]*?\b([a-z_][a-z0-9_]*)\s*\(", text, flags=re.M)
+    return sorted(set(n for n in names if n not in ("if", "while", "for", "sizeof")))
+
+
+@pytest.fixture(scope="module")
+def mop():
+    import paper_2501_11962_amd as m
+    if not os.path.exists(m.LIB_PATH):
+        from paper_2501_11962_amd import build
+        build.build()
+    return m
+
+
+def test_header_declares_the_four_path_calls():
+    names = declared_functions()
+    for n in ("veff_energy", "veff_grad", "bead_forces", "bead_hvp"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(mop):
+    L = mop.lib()
+    names = declared_functions()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(mop.EXPORTS)
+
+
+def test_strerror(mop):
+    L = mop.lib()
+    for code in (0, -1, -2, -3, -4, -5, -6, -7):
+        assert L.mop_strerror(code)
+    assert L.mop_strerror(-2).decode().startswith("cutoff")
+
+
+def test_system_check_accepts_workloads(mop):
+    for s in (W.cfg1(), W.cfg2(), W.cfg3(), W.tiny(), W.water_box(1002, 3)):
+        assert mop.system_check(s) == 0
+        assert mop.system_check(s, use_molecules=True) == 0
+
+
+def test_system_check_rejections(mop):
+    s = W.tiny()
+    bad = dict(s, rc=0.81)                      # >= box/2
+    assert mop.system_check(bad) == -2
+    bad = dict(s, rc=0.0)
+    assert mop.system_check(bad) == -2
+    t = s["type"].copy()
+    t[3] = 7
+    assert mop.system_check(dict(s, type=t)) == -3
+    m = s["mass"].copy()
+    m[0] = 0.0
+    assert mop.system_check(dict(s, mass=m)) == -1
+    # a ring of three bonded atoms is not a linear chain
+    ring = dict(s, bonds=np.array([[0, 1], [1, 2], [2, 0]]), bond_r0=np.full(3, 0.3),
+                bond_k=np.full(3, 1e3))
+    assert mop.system_check(ring) == -6
+    # explicit molecule keys make any topology acceptable
+    assert mop.system_check(ring, use_molecules=True) == 0
+    b = s["bonds"].copy()
+    b[0, 1] = s["Q"] + 5
+    assert mop.system_check(dict(s, bonds=b)) == -1
+    sig = np.full(17, 0.3)
+    assert mop.system_check(dict(s, sigma=sig, epsilon=sig)) == -3
+
+
+def test_ctx_create_reports_missing_device(mop):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    h = C.c_void_p()
+    assert mop.lib().mop_ctx_create(0, None, C.byref(h)) == -4
+
+
+def test_calls_reject_null_handles(mop):
+    L = mop.lib()
+    assert L.bead_forces(None, None, 1, None, None, None) == -1
+    assert L.veff_grad(None, None, 1, None, None, 0, 0.0, None) == -1
+    assert L.veff_energy(None, None, 1, None, None, None, None) == -1
+    assert L.bead_hvp(None, None, None, 1, None, None) == -1
+    assert L.mop_batch_create(0, None, None, C.byref(C.c_void_p())) == -1

@@ -1,0 +1,278 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 CPU oracle.
+
+Tolerances, relative L2 per bead: forces 1e-5, Hessian-vector products 1e-4, gradient
+1e-5; V_eff 1e-6 relative (FP32 pair forces enter V_eff through c*F); the FP64-only
+stages (bonds, residuals, sums) 1e-10 when no FP32 pair term contributes.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import path as OP
+from oracle.potential import Model
+
+pytestmark = pytest.mark.gpu
+
+TOL_F, TOL_HV, TOL_G, TOL_V = 1e-5, 1e-4, 1e-5, 1e-6
+
+
+@pytest.fixture(scope="module")
+def mop():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2501_11962_amd as m
+    m.lib()
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(mop):
+    return mop.Context()
+
+
+def rel(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def cuda(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x, np.float64)).cuda()
+
+
+def oracle_model(s, cl_oracle):
+    return cl_oracle.CellModel(s) if s["Q"] > 3000 else Model(s)
+
+
+SMALL = {
+    "tiny": lambda: W.tiny(),
+    "cfg1": W.cfg1,
+    "water300": lambda: W.water_box(300, seed=5, rc=0.6),
+    "cfg2": W.cfg2,
+    "water1002_cw03": lambda: W.water_box(1002, seed=9, rc=1.0),
+}
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.mark.parametrize("name", list(SMALL))
+def test_bead_forces_and_energy(name, mop, ctx, cl_oracle):
+    s = SMALL[name]()
+    R, _, _ = W.random_walk_path(s, 3, 11, 0.01)
+    say(f"[bead_forces] {name} Q={s['Q']} B=3")
+    sysm = mop.System(ctx, s)
+    plan = mop.Plan(sysm, 3)
+    F, U = mop.bead_forces(plan, cuda(R))
+    F, U = F.cpu().numpy(), U.cpu().numpy()
+    assert plan.status() == 0
+    m = oracle_model(s, cl_oracle)
+    for b in range(3):
+        Fo = m.forces(R[b])
+        e = rel(F[b], Fo)
+        eu = abs(U[b] - m.energy(R[b])) / max(abs(m.energy(R[b])), 1.0)
+        say(f"   bead {b}: force relL2 {e:.2e}  energy rel {eu:.2e}")
+        assert e < TOL_F
+        assert eu < TOL_F
+
+
+@pytest.mark.parametrize("name", list(SMALL))
+def test_bead_hvp(name, mop, ctx, cl_oracle):
+    s = SMALL[name]()
+    R, _, _ = W.random_walk_path(s, 2, 12, 0.01)
+    V = np.random.default_rng(3).standard_normal(R.shape) * 1e-3
+    say(f"[bead_hvp] {name}")
+    plan = mop.Plan(mop.System(ctx, s), 2)
+    HV = mop.bead_hvp(plan, cuda(R), cuda(V)).cpu().numpy()
+    m = oracle_model(s, cl_oracle)
+    for b in range(2):
+        e = rel(HV[b], m.hvp(R[b], V[b]))
+        say(f"   bead {b}: hvp relL2 {e:.2e}")
+        assert e < TOL_HV
+
+
+@pytest.mark.parametrize("name,N", [("tiny", 5), ("cfg1", 32), ("water300", 6), ("cfg2", 8)])
+def test_veff_energy_and_grad(name, N, mop, ctx, cl_oracle):
+    s = SMALL[name]()
+    sigma = 0.005 if name == "cfg1" else None
+    R, _, _ = W.random_walk_path(s, N, 21, sigma)
+    say(f"[veff] {name} N={N}")
+    plan = mop.Plan(mop.System(ctx, s), N)
+    Rt = cuda(R)
+    ve = mop.veff_energy(plan, Rt).cpu().numpy()
+    G, v = mop.veff_grad(plan, Rt)
+    G, v = G.cpu().numpy(), float(v.cpu().numpy()[0])
+    assert np.isfinite(G).all()
+    assert plan.status() == 0
+    m = oracle_model(s, cl_oracle)
+    Go, vo = OP.veff_grad(m, R)
+    vo2, u1o, eso = OP.veff(m, R)
+    say(f"   V_eff gpu {v:.10e} oracle {vo:.10e} rel {abs(v - vo) / abs(vo):.2e}")
+    assert abs(v - vo) < TOL_V * abs(vo)
+    assert abs(ve[0] - vo) < TOL_V * abs(vo)
+    assert abs(ve[1] - u1o) < TOL_F * max(abs(u1o), 1.0)
+    assert abs(ve[2] - eso) < TOL_V * abs(eso)
+    errs = [rel(G[n], Go[n]) for n in range(N)]
+    say(f"   G relL2 per bead: max {max(errs):.2e} mean {np.mean(errs):.2e}")
+    assert max(errs) < TOL_G
+
+
+def test_fp64_stages_without_pair_terms(mop, ctx):
+    """Charges and LJ switched off: only FP64 bonds, residuals and sums remain."""
+    s = W.water_box(300, seed=5, rc=0.6)
+    s = dict(s, charge=np.zeros(s["Q"]), epsilon=np.zeros(2))
+    N = 6
+    R, _, _ = W.random_walk_path(s, N, 4)
+    plan = mop.Plan(mop.System(ctx, s), N)
+    G, v = mop.veff_grad(plan, cuda(R))
+    m = Model(s)
+    Go, vo = OP.veff_grad(m, R)
+    assert abs(float(v.cpu()[0]) - vo) < 1e-10 * abs(vo)
+    assert rel(G.cpu().numpy(), Go) < 1e-10
+
+
+def test_single_bead_and_single_atom(mop, ctx):
+    s = W.cfg1()
+    R = s["x"][None]
+    plan = mop.Plan(mop.System(ctx, s), 4)
+    G, v = mop.veff_grad(plan, cuda(R))
+    m = Model(s)
+    assert rel(G.cpu().numpy()[0], -m.forces(R[0])) < TOL_F
+    assert abs(float(v.cpu()[0]) - m.energy(R[0])) < TOL_F * abs(m.energy(R[0]))
+    # one atom: no pairs at all
+    one = dict(Q=1, box=np.array([2.0, 2.0, 2.0]), x=np.array([[0.3, 0.4, 0.5]]),
+               mass=np.array([16.0]), charge=np.array([0.5]), type=np.array([0]),
+               sigma=np.array([0.3]), epsilon=np.array([0.5]), bonds=np.zeros((0, 2)),
+               bond_r0=np.zeros(0), bond_k=np.zeros(0), mol=np.array([0]),
+               molpos=np.array([0]), rc=0.9, eps_rf=78.0, eps_r=1.0, dt=0.001, nu=250.0, kT=2.5)
+    R1, _, _ = W.random_walk_path(one, 3, 1, 0.01)
+    p1 = mop.Plan(mop.System(ctx, one), 3)
+    G1, v1 = mop.veff_grad(p1, cuda(R1))
+    Go, vo = OP.veff_grad(Model(one), R1)
+    assert rel(G1.cpu().numpy(), Go) < 1e-12
+    assert abs(float(v1.cpu()[0]) - vo) < 1e-12 * abs(vo)
+
+
+def test_unwrapped_coordinates(mop, ctx):
+    s = W.cfg2()
+    R, _, _ = W.random_walk_path(s, 4, 5)
+    Rw = R + np.array([3.0, -2.0, 7.0]) * s["box"]
+    Rw[2] = np.mod(Rw[2], s["box"])
+    plan = mop.Plan(mop.System(ctx, s), 4)
+    G1, v1 = mop.veff_grad(plan, cuda(R))
+    G2, v2 = mop.veff_grad(plan, cuda(Rw))
+    m = Model(s)
+    Go, vo = OP.veff_grad(m, R)
+    assert rel(G2.cpu().numpy(), Go) < TOL_G
+    assert abs(float(v2.cpu()[0]) - vo) < TOL_V * abs(vo)
+
+
+@pytest.mark.parametrize("cw,zb,waves", [(0.35, 0.05, 1), (0.8, 0.3, 2), (0.5, 0.1, 8)])
+def test_plan_options_give_the_same_result(cw, zb, waves, mop, ctx):
+    s = W.water_box(3 * 900, seed=2, rc=0.9)
+    R, _, _ = W.random_walk_path(s, 3, 6)
+    plan = mop.Plan(mop.System(ctx, s), 3, col_width=cw, zbin=zb, waves=waves)
+    say(f"[options] cw={cw} zbin={zb} waves={waves} info={plan.info()}")
+    G, v = mop.veff_grad(plan, cuda(R))
+    Go, vo = OP.veff_grad(Model(s), R)
+    assert rel(G.cpu().numpy(), Go) < TOL_G
+
+
+def test_fd_mode_matches_oracle_fd(mop, ctx):
+    s = W.cfg1()
+    N, h = 5, 1e-3
+    R, _, _ = W.random_walk_path(s, N, 8, 0.005)
+    plan = mop.Plan(mop.System(ctx, s), N)
+    Gfd, _ = mop.veff_grad(plan, cuda(R), mode=1, fd_h=h)
+    m = Model(s)
+    Gofd = OP.veff_grad_fd(m, R, h)
+    Go, _ = OP.veff_grad(m, R)
+    e_fd = rel(Gfd.cpu().numpy(), Gofd)
+    say(f"[fd] gpu-FD vs oracle-FD relL2 {e_fd:.2e}; oracle FD vs exact {rel(Gofd, Go):.2e}")
+    assert e_fd < 1e-4
+
+
+def test_batch_matches_single_paths(mop, ctx):
+    specs = [(1002, 7, 31), (1503, 12, 32), (2001, 5, 33)]
+    plans, paths, refs = [], [], []
+    for Q, N, seed in specs:
+        s = W.water_box(Q, seed, rc=1.0 if Q > 1500 else 0.9)
+        R, _, _ = W.random_walk_path(s, N, seed + 100)
+        pl = mop.Plan(mop.System(ctx, s), N)
+        plans.append(pl)
+        paths.append(cuda(R))
+        refs.append(OP.veff_grad(Model(s), R))
+    bt = mop.Batch(plans, [sp[1] for sp in specs])
+    Gflat, v = bt.veff_grad(bt.pack(paths))
+    assert bt.status() == 0
+    for k, (G, (Go, vo)) in enumerate(zip(bt.unpack(Gflat), refs)):
+        e = rel(G.cpu().numpy(), Go)
+        say(f"[batch] path {k} G relL2 {e:.2e} V_eff rel {abs(float(v[k]) - vo) / abs(vo):.2e}")
+        assert e < TOL_G
+        assert abs(float(v[k]) - vo) < TOL_V * abs(vo)
+
+
+def test_nonfinite_input_sets_status(mop, ctx):
+    s = W.cfg1()
+    R, _, _ = W.random_walk_path(s, 3, 1, 0.005)
+    R[1, 5, 0] = np.nan
+    plan = mop.Plan(mop.System(ctx, s), 3)
+    plan.clear_status()
+    mop.veff_grad(plan, cuda(R))
+    assert plan.status() & mop.MOP_DEV_NONFINITE
+    plan.clear_status()
+    R2, _, _ = W.random_walk_path(s, 3, 1, 0.005)
+    mop.veff_grad(plan, cuda(R2))
+    assert plan.status() == 0
+
+
+def test_autograd_function(mop, ctx):
+    import torch
+    s = W.cfg1()
+    R, _, _ = W.random_walk_path(s, 4, 2, 0.005)
+    plan = mop.Plan(mop.System(ctx, s), 4)
+    Rt = cuda(R).requires_grad_(True)
+    v = mop.VeffFn.apply(Rt, plan)
+    (2.5 * v).backward()
+    G, v2 = mop.veff_grad(plan, cuda(R))
+    # two calls may sum FP32 pair terms in a different order (atomic bin ranks)
+    scale = float(G.abs().max())
+    assert torch.allclose(Rt.grad, 2.5 * G, rtol=1e-5, atol=1e-6 * scale)
+    assert abs(float(v) - float(v2[0])) < 1e-9 * abs(float(v2[0]))
+
+
+def test_gpu_invariants(mop, ctx):
+    """Properties that hold at any size, on GPU outputs alone."""
+    s = W.cfg3()
+    R, _, _ = W.random_walk_path(s, 2, 3)
+    plan = mop.Plan(mop.System(ctx, s), 2)
+    F, _ = mop.bead_forces(plan, cuda(R))
+    F = F.cpu().numpy().astype(np.float64)
+    for b in range(2):
+        assert np.linalg.norm(F[b].sum(0)) < 1e-4 * np.linalg.norm(F[b]) / math.sqrt(s["Q"]) * 100
+    rng = np.random.default_rng(1)
+    U_, V_ = rng.standard_normal(R.shape) * 1e-3, rng.standard_normal(R.shape) * 1e-3
+    HU = mop.bead_hvp(plan, cuda(R), cuda(U_)).cpu().numpy().astype(np.float64)
+    HV = mop.bead_hvp(plan, cuda(R), cuda(V_)).cpu().numpy().astype(np.float64)
+    for b in range(2):
+        a, c = np.sum(U_[b] * HV[b]), np.sum(V_[b] * HU[b])
+        assert abs(a - c) < 1e-5 * np.linalg.norm(HU[b]) * np.linalg.norm(V_[b])
+
+
+@pytest.mark.parametrize("cfg,N", [("cfg3", 3)])
+def test_cfg3_parity(cfg, N, mop, ctx, cl_oracle):
+    s, R = W.make_config(cfg, N)
+    say(f"[{cfg}] Q={s['Q']} N={N}")
+    plan = mop.Plan(mop.System(ctx, s), N)
+    G, v = mop.veff_grad(plan, cuda(R))
+    m = cl_oracle.CellModel(s)
+    Go, vo = OP.veff_grad(m, R)
+    errs = [rel(G.cpu().numpy()[n], Go[n]) for n in range(N)]
+    say(f"   G relL2 {errs}  V_eff rel {abs(float(v[0]) - vo) / abs(vo):.2e}")
+    assert max(errs) < TOL_G
+    assert abs(float(v[0]) - vo) < TOL_V * abs(vo)
