@@ -167,8 +167,10 @@ def main():
             Gref = G.clone()
             g.replay()
             torch.cuda.synchronize()
-            if not torch.equal(G, Gref) and not torch.allclose(G, Gref, rtol=1e-6, atol=0):
-                raise RuntimeError("graph replay differs from eager")
+            # replays and eager calls may sum FP32 pair terms in a different order
+            err = float((G - Gref).norm() / Gref.norm())
+            if not err < 1e-6:
+                raise RuntimeError(f"graph replay differs from eager (rel L2 {err:.2e})")
             torch.cuda.synchronize()
             e0.record()
             for _ in range(args.steps):

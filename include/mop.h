@@ -99,10 +99,15 @@ typedef struct {
 /*
  * Neighbour-search options of a plan (0 = default for every field).
  *   col_width   width (nm) of the x-y columns atoms are binned into; 8-atom clusters
- *               are cut along z inside each column.  Default 0.5 nm.
+ *               are cut along z inside each column.  Default 0.4 nm.
  *   zbin        height (nm) of the z bins used to sort columns.  Default 0.1 nm.
  *   waves       waves per workgroup of the pair kernels (1, 2, 4, 8).  Default 4.
+ *   flags       MOP_PLAN_NEWTON3: evaluate each pair once (Newton's third law) and
+ *               gather the partner's share with atomic adds; summation order then
+ *               depends on scheduling.  Default: every pair from both sides without
+ *               atomics, which is the faster variant on MI355X.
  */
+#define MOP_PLAN_NEWTON3 1
 typedef struct {
     double col_width;
     double zbin;

@@ -67,6 +67,20 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
     return s;
 }
 
+// Block-wide max of a double (blockDim.x == EWB), result valid in thread 0.
+__device__ __forceinline__ double block_max(double v, double* sh) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v = fmax(v, __shfl_xor(v, m, 64));
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    __syncthreads();
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) s = fmax(s, sh[k]);
+    return s;
+}
+
 // Harmonic bonds of atom i in FP64 (each bond is listed for both of its atoms).
 // Adds the force on i to f; adds k/2 (r - r0)^2 of bonds with partner j > i to *e.
 __device__ __forceinline__ void bond_force(const SysDev& s, const double* Rb, const double* Db,

@@ -10,7 +10,8 @@
 
 namespace mop {
 
-// Zero the bin histograms and the per-bead max |d|^2 of every segment.
+// Zero the bin histograms, the slot-order pair sums and (zero_dmax) the per-bead
+// max |d|^2 of every segment.
 __global__ void __launch_bounds__(EWB) k_zero(const SegDev* __restrict__ segs, Launch L, char* ws,
                                               int zero_dmax) {
     const int blk = blockIdx.x;
@@ -18,10 +19,13 @@ __global__ void __launch_bounds__(EWB) k_zero(const SegDev* __restrict__ segs, L
     const SegDev& sg = segs[p];
     const size_t idx = (size_t)(blk - L.pf[p]) * EWB + threadIdx.x;
     const size_t n1 = (size_t)L.nb[p] * sg.s.ncol * sg.s.nzb;
+    const size_t n2 = (size_t)L.nb[p] * 3 * sg.s.S;
     if (idx < n1) {
         wsp<int>(ws, sg.o_bincnt)[idx] = 0;
-    } else if (zero_dmax && idx - n1 < (size_t)sg.maxN) {
-        wsp<unsigned long long>(ws, sg.o_dmax)[idx - n1] = 0ull;
+    } else if (idx - n1 < n2) {
+        wsp<float>(ws, sg.o_fs)[idx - n1] = 0.0f;
+    } else if (zero_dmax && idx - n1 - n2 < (size_t)sg.maxN) {
+        wsp<unsigned long long>(ws, sg.o_dmax)[idx - n1 - n2] = 0ull;
     }
 }
 
@@ -163,6 +167,7 @@ void run_binning(const SegDev* dsegs, const SegDev* hsegs, const Launch& base, c
     L.pf[0] = 0;
     for (int p = 0; p < base.nseg; ++p) {
         const size_t n = (size_t)base.nb[p] * hsegs[p].s.ncol * hsegs[p].s.nzb +
+                         (size_t)base.nb[p] * 3 * hsegs[p].s.S +
                          (fdsign == 0 ? hsegs[p].maxN : 0);
         L.pf[p + 1] = L.pf[p] + (int)((n + EWB - 1) / EWB);
     }

@@ -8,37 +8,151 @@
 //      cluster range covering the z window [zlo - r, zhi + r] (two ranges when the
 //      window wraps around the box).
 //   2. Candidate clusters are listed in LDS; 8 of them (64 atoms) are loaded per step,
-//      one atom per lane.  Each atom is converted to FP32 coordinates relative to the
-//      i-cluster's first atom (exact integer minimum image, then one rounding) and kept
-//      when it lies within the cutoff of the i-cluster's bounding box.  Survivors are
-//      compacted (ballot + mbcnt) into a per-wave LDS ring.
+//      one atom per lane, converted to FP32 coordinates relative to the i-cluster's box
+//      centre (exact integer minimum image, then one rounding) and kept when within the
+//      cutoff of the i-cluster's bounding box.  Survivors are compacted (ballot + mbcnt)
+//      into a per-wave LDS ring.
 //   3. Every 64 ring entries, 8 steps of 8 j-atoms x 8 i-atoms (lane = 8*i + j) evaluate
 //      the pair terms; each lane accumulates a partial sum for its i atom.
-//   4. Partial sums are reduced over the 8 j lanes and written in original atom order.
-// Every pair is evaluated from both sides (no Newton-3 scatter): no atomics, and
-// results do not depend on scheduling.
+//   4. Partial sums are reduced over the 8 j lanes.
+//
+// Two variants:
+//   N3 = 1 (opt-in): Newton's third law.  A wave takes only clusters with a larger
+//      index than its own, so every pair of distinct clusters is evaluated once.  The
+//      j-side contribution of a step is added to the ring entry with an LDS atomic and,
+//      once per 64 entries, flushed to a slot-order FP32 buffer with one global atomic
+//      per entry; i-sums are added the same way.  The own cluster is one 8 x 8 block
+//      evaluated from both sides.  Summation order depends on scheduling.
+//   N3 = 0 (default): every pair evaluated from both sides; no atomics; run-to-run
+//      reproducible for a given binning.  Results go straight to original atom order.
+//      Measured on MI355X (150,000 atoms, 15 beads), this is the faster variant: the LDS
+//      atomics of N3 (8 lanes on one address) serialise, and the global flush of the
+//      j-side sums (three float atomics per entry) costs about as much as the pair work
+//      it saves.
 //
 // Pair terms, d = x_j - x_i, r = |d|, shifted-force LJ + reaction field:
 //   g = phi_sf'(r)/r = (a12 r^-6 + a6) r^-8 + qq (2 k_rf - r^-3) + C1 r^-1,
 //       C1 = -phi'(r_c) = csf + qq crf1
 //   h = (phi'' - phi_sf'/r)/r^2 = (b12 r^-6 + b6) r^-10 + 3 qq r^-5 - C1 r^-3
-//   F_i += g d,   (H v)_i += g (v_i - v_j) + h (d . (v_i - v_j)) d
+//   F_i += g d,   (H v)_i += g (v_i - v_j) + h (d . (v_i - v_j)) d   (j: the opposite)
+#include <algorithm>
+
 #include "device_common.h"
 #include "launch.h"
 
 namespace mop {
 
-template <int MODE, int PW>
+// Ring fields (one LDS array [field][entry] per wave; ints stored as float bits).
+constexpr int F_X = 0, F_Y = 1, F_Z = 2, F_Q = 3, F_K = 4, F_T = 5, F_S = 6, F_J = 7;
+
+template <int MODE, int N3>
+struct Fields {
+    static constexpr int V = N3 ? 10 : 7;                    // v_j (HVP only)
+    static constexpr int NF = MODE == 1 ? V + 3 : (N3 ? 10 : 7);
+};
+
+struct IAtom {
+    float x, y, z, q, vx, vy, vz;
+    uint32_t ux, uy, uz;
+    int key2, tiN;
+    bool v;
+};
+
+struct PairK {
+    float sx, sy, sz, rc2, krf2, crf1, krf, crf, e0rf;
+};
+
+// One pair term for lane atom I and j-atom (jx, jy, jz): coordinates relative to the
+// box centre, or (EX) raw fixed-point bits.  The contribution to atom i (force: g d;
+// HVP: g (v_i - v_j) + h (d . (v_i - v_j)) d) is added to (ax, ay, az) with fused
+// multiply-adds; with T_OUT it is also returned in t (for the j side).  tabrow points
+// at the type-table row of atom i.
+template <int MODE, bool EX, bool WANTE, bool T_OUT>
+__device__ __forceinline__ void pair_term(const IAtom& I, const PairK& P, const float4* tabrow,
+                                          float jx, float jy, float jz,
+                                          float qj, int kj, int tj, float vjx, float vjy,
+                                          float vjz, bool valid, float& ax, float& ay,
+                                          float& az, float& tx, float& ty, float& tz,
+                                          float& en) {
+    float dx, dy, dz;
+    if (EX) {
+        dx = (float)(int)(__float_as_uint(jx) - I.ux) * P.sx;
+        dy = (float)(int)(__float_as_uint(jy) - I.uy) * P.sy;
+        dz = (float)(int)(__float_as_uint(jz) - I.uz) * P.sz;
+    } else {
+        dx = jx - I.x;
+        dy = jy - I.y;
+        dz = jz - I.z;
+    }
+    const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+    const bool in = valid & I.v & (r2 < P.rc2) & ((unsigned)(I.key2 - kj) > 4u);
+    // masked lanes (self pair at r = 0, stale ring entries) may form inf/NaN here; every
+    // result they feed is replaced by 0 through a select below, never multiplied
+    const float r2s = r2;
+    const float rinv = __builtin_amdgcn_rsqf(r2s);
+    const float rinv2 = rinv * rinv;
+    const float rinv6 = rinv2 * rinv2 * rinv2;
+    const float rinv3 = rinv2 * rinv;
+    const float4 T = tabrow[2 * tj];
+    const float qq = I.q * qj;
+    const float C1 = fmaf(qq, P.crf1, T.z);
+    float g = fmaf(T.x, rinv6, T.y) * rinv6 * rinv2;
+    g = fmaf(qq, P.krf2 - rinv3, g);
+    g = fmaf(C1, rinv, g);
+    g = in ? g : 0.0f;
+    if (MODE == 0) {
+        if (T_OUT) {
+            tx = g * dx;
+            ty = g * dy;
+            tz = g * dz;
+            ax += tx;
+            ay += ty;
+            az += tz;
+        } else {
+            ax = fmaf(g, dx, ax);
+            ay = fmaf(g, dy, ay);
+            az = fmaf(g, dz, az);
+        }
+        if (WANTE) {
+            const float4 T2 = tabrow[2 * tj + 1];
+            const float r = r2s * rinv;
+            float e = fmaf(T2.z, rinv6, -T2.w) * rinv6;
+            const float erf = rinv + P.krf * r2s - P.crf + P.e0rf + P.crf1 * r;
+            e = fmaf(qq, erf, e);
+            e += fmaf(T.z, r, T.w);
+            en = in ? e : 0.0f;
+        }
+    } else {
+        const float4 T2 = tabrow[2 * tj + 1];
+        const float rinv4 = rinv2 * rinv2;
+        float h = fmaf(T2.x, rinv6, T2.y) * rinv6 * rinv4;
+        h = fmaf(3.0f * qq, rinv3 * rinv2, h);
+        h = fmaf(-C1, rinv3, h);
+        h = in ? h : 0.0f;
+        const float dvx = I.vx - vjx, dvy = I.vy - vjy, dvz = I.vz - vjz;
+        const float sd = fmaf(dx, dvx, fmaf(dy, dvy, dz * dvz));
+        const float hs = h * sd;
+        if (T_OUT) {
+            tx = fmaf(g, dvx, hs * dx);
+            ty = fmaf(g, dvy, hs * dy);
+            tz = fmaf(g, dvz, hs * dz);
+            ax += tx;
+            ay += ty;
+            az += tz;
+        } else {
+            ax = fmaf(g, dvx, fmaf(hs, dx, ax));
+            ay = fmaf(g, dvy, fmaf(hs, dy, ay));
+            az = fmaf(g, dvz, fmaf(hs, dz, az));
+        }
+    }
+}
+
+template <int MODE, int PW, int N3>
 __global__ void __launch_bounds__(64 * PW) k_pair(const SegDev* __restrict__ segs, Launch L,
                                                  char* __restrict__ ws, int outsel, int energy_bead) {
-    constexpr int TT = MAXTYPES * MAXTYPES;
-    constexpr int VR = MODE == 1 ? RING : 1;
-    __shared__ float4 s_tab[TT];
-    __shared__ float4 s_tab2[TT];
-    __shared__ float s_rx[PW][RING], s_ry[PW][RING], s_rz[PW][RING], s_rq[PW][RING];
-    __shared__ int s_rk[PW][RING], s_rt[PW][RING];
-    __shared__ float s_vx[PW][VR], s_vy[PW][VR], s_vz[PW][VR];
-    __shared__ int s_cl[PW][CLIST];
+    using FL = Fields<MODE, N3>;
+    constexpr int NF = FL::NF, FV = FL::V;
+    extern __shared__ float4 s_dyn[];
 
     const int nblk = L.pf[L.nseg];
     const int per = (nblk + 7) >> 3;
@@ -48,9 +162,13 @@ __global__ void __launch_bounds__(64 * PW) k_pair(const SegDev* __restrict__ seg
     const int p = find_seg(L, lblk);
     const SegDev* __restrict__ sg = segs + p;
     const int nt = sg->s.nt;
+    const int ntm = L.ntmax;
+    float4* s_tab = s_dyn;  // interleaved: [2k] pair constants, [2k+1] second-derivative/energy
+    float* s_ring = reinterpret_cast<float*>(s_dyn + 2 * ntm * ntm);
+    int* s_cl = reinterpret_cast<int*>(s_ring + PW * NF * RING);
     for (int t = threadIdx.x; t < nt * nt; t += 64 * PW) {
-        s_tab[t] = sg->s.tab[t];
-        s_tab2[t] = sg->s.tab2[t];
+        s_tab[2 * t] = sg->s.tab[t];
+        s_tab[2 * t + 1] = sg->s.tab2[t];
     }
     __syncthreads();  // the only block barrier: waves are independent from here on
 
@@ -66,13 +184,25 @@ __global__ void __launch_bounds__(64 * PW) k_pair(const SegDev* __restrict__ seg
     const int* __restrict__ colstart = wsp<const int>(ws, sg->o_colstart) + (size_t)b * (ncol + 1);
     const int* __restrict__ binoff = wsp<const int>(ws, sg->o_binoff) + (size_t)b * ncol * (nzb + 1);
     const float4* __restrict__ vs = wsp<const float4>(ws, sg->o_vs) + (size_t)b * S;
+    float* __restrict__ fsx = wsp<float>(ws, sg->o_fs) + (size_t)b * 3 * S;
+    float* __restrict__ fsy = fsx + S;
+    float* __restrict__ fsz = fsy + S;
     const int nslots = colstart[ncol];
     if (c * CLUSTER >= nslots) return;
 
     const bool wantE = MODE == 0 && (energy_bead == -2 || energy_bead == b);
-    const float sx = sg->s.sc[0], sy = sg->s.sc[1], sz = sg->s.sc[2];
-    const float rc2 = sg->s.rc2, rcs = sg->s.rcs, rcs2 = sg->s.rcs2;
-    const float krf2 = sg->s.krf2, crf1 = sg->s.crf1;
+    PairK P;
+    P.sx = sg->s.sc[0];
+    P.sy = sg->s.sc[1];
+    P.sz = sg->s.sc[2];
+    P.rc2 = sg->s.rc2;
+    P.krf2 = sg->s.krf2;
+    P.crf1 = sg->s.crf1;
+    P.krf = sg->s.krf;
+    P.crf = sg->s.crf;
+    P.e0rf = sg->s.e0rf;
+    const float sx = P.sx, sy = P.sy, sz = P.sz;
+    const float rcs = sg->s.rcs, rcs2 = sg->s.rcs2;
 
     // ---- the i-cluster ------------------------------------------------------------
     const int isub = lane >> 3, jslot = lane & 7;
@@ -80,27 +210,31 @@ __global__ void __launch_bounds__(64 * PW) k_pair(const SegDev* __restrict__ seg
     const uint4 ui = upos[si];
     const int2 mi = umeta[si];
     const uint4 ref = upos[c * CLUSTER];
-    const bool vi = mi.x != DUMMY_KEY;
-    const float qi = __uint_as_float(ui.w);
-    const int keyi2 = mi.x + 2;
-    const int tiN = mi.y * nt;
-    float vxi = 0.f, vyi = 0.f, vzi = 0.f;
+    IAtom I;
+    I.v = mi.x != DUMMY_KEY;
+    I.q = __uint_as_float(ui.w);
+    I.key2 = mi.x + 2;
+    I.tiN = mi.y * nt;
+    const float4* tabrow = s_tab + 2 * I.tiN;
+    I.ux = ui.x;
+    I.uy = ui.y;
+    I.uz = ui.z;
+    I.vx = I.vy = I.vz = 0.0f;
     if (MODE == 1) {
         const float4 v4 = vs[si];
-        vxi = v4.x;
-        vyi = v4.y;
-        vzi = v4.z;
+        I.vx = v4.x;
+        I.vy = v4.y;
+        I.vz = v4.z;
     }
-    // bounding box of the cluster in coordinates relative to its first atom, then
-    // re-referenced to the box centre uc (fixed point)
+    // bounding box relative to the first atom, then re-referenced to its centre uc
     float lox, hix, loy, hiy, loz, hiz;
     auto bbox = [&](float x, float y, float z) {
-        lox = vi ? x : 3.0e38f;
-        hix = vi ? x : -3.0e38f;
-        loy = vi ? y : 3.0e38f;
-        hiy = vi ? y : -3.0e38f;
-        loz = vi ? z : 3.0e38f;
-        hiz = vi ? z : -3.0e38f;
+        lox = I.v ? x : 3.0e38f;
+        hix = I.v ? x : -3.0e38f;
+        loy = I.v ? y : 3.0e38f;
+        hiy = I.v ? y : -3.0e38f;
+        loz = I.v ? z : 3.0e38f;
+        hiz = I.v ? z : -3.0e38f;
 #pragma unroll
         for (int m = 8; m < 64; m <<= 1) {
             lox = fminf(lox, __shfl_xor(lox, m, 64));
@@ -116,10 +250,10 @@ __global__ void __launch_bounds__(64 * PW) k_pair(const SegDev* __restrict__ seg
     const uint32_t ucx = ref.x + (uint32_t)(long long)rintf(0.5f * (lox + hix) / sx);
     const uint32_t ucy = ref.y + (uint32_t)(long long)rintf(0.5f * (loy + hiy) / sy);
     const uint32_t ucz = ref.z + (uint32_t)(long long)rintf(0.5f * (loz + hiz) / sz);
-    const float xi = (float)(int)(ui.x - ucx) * sx;
-    const float yi = (float)(int)(ui.y - ucy) * sy;
-    const float zi = (float)(int)(ui.z - ucz) * sz;
-    bbox(xi, yi, zi);
+    I.x = (float)(int)(ui.x - ucx) * sx;
+    I.y = (float)(int)(ui.y - ucy) * sy;
+    I.z = (float)(int)(ui.z - ucz) * sz;
+    bbox(I.x, I.y, I.z);
     // Coordinates relative to the centre give exact pair differences when
     // extent + search radius < L/2 along every axis; otherwise each pair difference is
     // taken from the fixed-point coordinates (small boxes, sparse columns).
@@ -142,7 +276,6 @@ __global__ void __launch_bounds__(64 * PW) k_pair(const SegDev* __restrict__ seg
         zwrap = zlo > zhi;
         if (zwrap && zb1 + 1 >= zb0) fullz = true;
     }
-    // bounding-box centre / half widths for the column test
     const float bcx = 0.5f * (lox + hix), bhx = 0.5f * (hix - lox);
     const float bcy = 0.5f * (loy + hiy), bhy = 0.5f * (hiy - loy);
     const float xref = (float)ucx * sx, yref = (float)ucy * sy;
@@ -150,103 +283,118 @@ __global__ void __launch_bounds__(64 * PW) k_pair(const SegDev* __restrict__ seg
     const float cwx = sg->s.cw[0], cwy = sg->s.cw[1];
 
     float ax = 0.f, ay = 0.f, az = 0.f;
-    double eacc = 0.0;
-    int wp = 0, rp = 0;  // ring write / read counters (uniform)
+    float eacc = 0.0f;
+    double eacc64 = 0.0;
+    int wp = 0, rp = 0;  // ring write / read counters (uniform); rp stays a multiple of 64
 
-    float* rx = s_rx[wave];
-    float* ry = s_ry[wave];
-    float* rz = s_rz[wave];
-    float* rq = s_rq[wave];
-    int* rk = s_rk[wave];
-    int* rt = s_rt[wave];
-    float* rvx = s_vx[wave];
-    float* rvy = s_vy[wave];
-    float* rvz = s_vz[wave];
-    int* clist = s_cl[wave];
+    float* ring = s_ring + wave * NF * RING;
+    int* clist = s_cl + wave * CLIST;
     // Ring entries past the valid count are read by the last step of an evaluation and
     // masked by a select on g and h; masked products are still formed (0 * dx, 0 * dv),
     // so every field such an entry can feed must hold a finite value, and the type
     // field a valid table index: clear the ring once.
-    for (int e = lane; e < RING; e += 64) {
-        rx[e] = 0.0f;
-        ry[e] = 0.0f;
-        rz[e] = 0.0f;
-        rq[e] = 0.0f;
-        rk[e] = 0;
-        rt[e] = 0;
-        if (MODE == 1) {
-            rvx[e] = 0.0f;
-            rvy[e] = 0.0f;
-            rvz[e] = 0.0f;
-        }
-    }
+    for (int e = lane; e < NF * RING; e += 64) ring[e] = 0.0f;
     wave_sync();
-    const float krf = sg->s.krf, crf = sg->s.crf, e0rf = sg->s.e0rf;
+
+    // ---- own cluster (N3): one 8 x 8 block, both sides, weight 1/2 for energies ----
+    if (N3) {
+        const int sj = c * CLUSTER + jslot;
+        const uint4 uj = upos[sj];
+        const int2 mj = umeta[sj];
+        float jx, jy, jz, vjx = 0.f, vjy = 0.f, vjz = 0.f;
+        if (exact) {
+            jx = __uint_as_float(uj.x);
+            jy = __uint_as_float(uj.y);
+            jz = __uint_as_float(uj.z);
+        } else {
+            jx = (float)(int)(uj.x - ucx) * sx;
+            jy = (float)(int)(uj.y - ucy) * sy;
+            jz = (float)(int)(uj.z - ucz) * sz;
+        }
+        if (MODE == 1) {
+            const float4 v4 = vs[sj];
+            vjx = v4.x;
+            vjy = v4.y;
+            vjz = v4.z;
+        }
+        float tx, ty, tz, en = 0.f;
+        const bool vj = mj.x != DUMMY_KEY;
+        const float qj = __uint_as_float(uj.w);
+        if (exact) {
+            if (wantE)
+                pair_term<MODE, true, true, false>(I, P, tabrow, jx, jy, jz, qj, mj.x, mj.y, vjx,
+                                            vjy, vjz, vj, ax, ay, az, tx, ty, tz, en);
+            else
+                pair_term<MODE, true, false, false>(I, P, tabrow, jx, jy, jz, qj, mj.x, mj.y, vjx,
+                                             vjy, vjz, vj, ax, ay, az, tx, ty, tz, en);
+        } else {
+            if (wantE)
+                pair_term<MODE, false, true, false>(I, P, tabrow, jx, jy, jz, qj, mj.x, mj.y, vjx,
+                                             vjy, vjz, vj, ax, ay, az, tx, ty, tz, en);
+            else
+                pair_term<MODE, false, false, false>(I, P, tabrow, jx, jy, jz, qj, mj.x, mj.y, vjx,
+                                              vjy, vjz, vj, ax, ay, az, tx, ty, tz, en);
+        }
+        eacc += 0.5f * en;
+    }
 
     // ---- 8 j-atoms x 8 i-atoms per step from ring entries [base, base + count) ------
-    auto eval_t = [&]<bool EX>(int base, int nsteps, int count) {
+    // base is a multiple of 64, so reads of a chunk never wrap and every field of every
+    // step is one immediate offset from the same address.
+    auto eval_t = [&]<bool EX, bool WE, bool FULL>(int base, int count) {
+        float* rb = ring + (base & (RING - 1)) + jslot;
+        const int nsteps = FULL ? 8 : (count + 7) >> 3;
+#pragma unroll
         for (int s = 0; s < nsteps; ++s) {
-            const int idx = s * 8 + jslot;
-            const int e = (base + idx) & (RING - 1);
-            float dx, dy, dz;
-            if (EX) {
-                dx = (float)(int)(__float_as_uint(rx[e]) - ui.x) * sx;
-                dy = (float)(int)(__float_as_uint(ry[e]) - ui.y) * sy;
-                dz = (float)(int)(__float_as_uint(rz[e]) - ui.z) * sz;
-            } else {
-                dx = rx[e] - xi;
-                dy = ry[e] - yi;
-                dz = rz[e] - zi;
+            const int o = s * 8;
+            const float jx = rb[F_X * RING + o], jy = rb[F_Y * RING + o], jz = rb[F_Z * RING + o];
+            const float qj = rb[F_Q * RING + o];
+            const int kj = __float_as_int(rb[F_K * RING + o]);
+            const int tj = __float_as_int(rb[F_T * RING + o]);
+            float vjx = 0.f, vjy = 0.f, vjz = 0.f;
+            if (MODE == 1) {
+                vjx = rb[FV * RING + o];
+                vjy = rb[(FV + 1) * RING + o];
+                vjz = rb[(FV + 2) * RING + o];
             }
-            const float qj = rq[e];
-            const int kj = rk[e], tj = rt[e];
-            const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-            const bool in = (idx < count) & vi & (r2 < rc2) & ((unsigned)(keyi2 - kj) > 4u);
-            const float r2s = in ? r2 : 1.0f;
-            const float rinv = __builtin_amdgcn_rsqf(r2s);
-            const float rinv2 = rinv * rinv;
-            const float rinv6 = rinv2 * rinv2 * rinv2;
-            const float rinv3 = rinv2 * rinv;
-            const float4 T = s_tab[tiN + tj];
-            const float qq = qi * qj;
-            const float C1 = fmaf(qq, crf1, T.z);
-            float g = fmaf(T.x, rinv6, T.y) * rinv6 * rinv2;
-            g = fmaf(qq, krf2 - rinv3, g);
-            g = fmaf(C1, rinv, g);
-            g = in ? g : 0.0f;
-            if (MODE == 0) {
-                ax = fmaf(g, dx, ax);
-                ay = fmaf(g, dy, ay);
-                az = fmaf(g, dz, az);
-                if (wantE) {
-                    const float4 T2 = s_tab2[tiN + tj];
-                    const float r = r2s * rinv;
-                    float en = fmaf(T2.z, rinv6, -T2.w) * rinv6;
-                    const float erf = rinv + krf * r2s - crf + e0rf + crf1 * r;
-                    en = fmaf(qq, erf, en);
-                    en += fmaf(T.z, r, T.w);
-                    eacc += in ? (double)en : 0.0;
-                }
-            } else {
-                const float4 T2 = s_tab2[tiN + tj];
-                const float rinv4 = rinv2 * rinv2;
-                float h = fmaf(T2.x, rinv6, T2.y) * rinv6 * rinv4;
-                h = fmaf(3.0f * qq, rinv3 * rinv2, h);
-                h = fmaf(-C1, rinv3, h);
-                h = in ? h : 0.0f;
-                const float dvx = vxi - rvx[e], dvy = vyi - rvy[e], dvz = vzi - rvz[e];
-                const float sd = fmaf(dx, dvx, fmaf(dy, dvy, dz * dvz));
-                const float hs = h * sd;
-                ax = fmaf(g, dvx, fmaf(hs, dx, ax));
-                ay = fmaf(g, dvy, fmaf(hs, dy, ay));
-                az = fmaf(g, dvz, fmaf(hs, dz, az));
+            float tx, ty, tz, en = 0.f;
+            pair_term<MODE, EX, WE, N3 == 1>(I, P, tabrow, jx, jy, jz, qj, kj, tj, vjx, vjy, vjz,
+                                             FULL || o + jslot < count, ax, ay, az, tx, ty, tz, en);
+            if (WE) eacc += N3 ? en : 0.5f * en;
+            if (N3) {
+                __hip_atomic_fetch_add(rb + (F_J + 0) * RING + o, tx, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WAVEFRONT);
+                __hip_atomic_fetch_add(rb + (F_J + 1) * RING + o, ty, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WAVEFRONT);
+                __hip_atomic_fetch_add(rb + (F_J + 2) * RING + o, tz, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WAVEFRONT);
+            }
+        }
+        if (WE) {  // FP32 partial of at most 64 pair terms per lane, summed in FP64
+            eacc64 += (double)eacc;
+            eacc = 0.0f;
+        }
+        if (N3) {
+            // j-side sums of this chunk (stored with the sign of the i side) go to the
+            // slot-order buffer, one entry per lane
+            wave_sync();
+            if (FULL || lane < count) {
+                const int e = (base & (RING - 1)) + lane;
+                const int slot = __float_as_int(ring[F_S * RING + e]);
+                unsafeAtomicAdd(fsx + slot, -ring[(F_J + 0) * RING + e]);
+                unsafeAtomicAdd(fsy + slot, -ring[(F_J + 1) * RING + e]);
+                unsafeAtomicAdd(fsz + slot, -ring[(F_J + 2) * RING + e]);
             }
         }
     };
-
-    auto eval = [&](int base, int nsteps, int count) {
-        if (exact) eval_t.template operator()<true>(base, nsteps, count);
-        else eval_t.template operator()<false>(base, nsteps, count);
+    auto eval = [&]<bool FULL>(int base, int count) {
+        if (exact) {
+            if (wantE) eval_t.template operator()<true, true, FULL>(base, count);
+            else eval_t.template operator()<true, false, FULL>(base, count);
+        } else {
+            if (wantE) eval_t.template operator()<false, true, FULL>(base, count);
+            else eval_t.template operator()<false, false, FULL>(base, count);
+        }
     };
 
     // ---- candidate clusters [0, T) of clist --------------------------------------
@@ -255,10 +403,10 @@ __global__ void __launch_bounds__(64 * PW) k_pair(const SegDev* __restrict__ seg
             const int ci = q + (lane >> 3);
             bool pass = false;
             float jx = 0.f, jy = 0.f, jz = 0.f, jq = 0.f;
-            int jk = 0, jt = 0;
+            int jk = 0, jt = 0, slot = 0;
             float4 jv = make_float4(0.f, 0.f, 0.f, 0.f);
             if (ci < T) {
-                const int slot = clist[ci] * CLUSTER + (lane & 7);
+                slot = clist[ci] * CLUSTER + (lane & 7);
                 const uint4 uj = upos[slot];
                 const int2 mj = umeta[slot];
                 if (MODE == 1) jv = vs[slot];
@@ -283,24 +431,31 @@ __global__ void __launch_bounds__(64 * PW) k_pair(const SegDev* __restrict__ seg
                                                       __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
             wave_sync();  // previous reads of the ring are done before it is overwritten
             if (pass) {
-                const int e = (wp + off) & (RING - 1);
-                rx[e] = jx;
-                ry[e] = jy;
-                rz[e] = jz;
-                rq[e] = jq;
-                rk[e] = jk;
-                rt[e] = jt;
+                float* re = ring + ((wp + off) & (RING - 1));
+                re[F_X * RING] = jx;
+                re[F_Y * RING] = jy;
+                re[F_Z * RING] = jz;
+                re[F_Q * RING] = jq;
+                re[F_K * RING] = __int_as_float(jk);
+                re[F_T * RING] = __int_as_float(jt);
+                re[F_S * RING] = __int_as_float(slot);
+                if (N3) {
+                    re[(F_J + 0) * RING] = 0.0f;
+                    re[(F_J + 1) * RING] = 0.0f;
+                    re[(F_J + 2) * RING] = 0.0f;
+                }
                 if (MODE == 1) {
-                    rvx[e] = jv.x;
-                    rvy[e] = jv.y;
-                    rvz[e] = jv.z;
+                    re[FV * RING] = jv.x;
+                    re[(FV + 1) * RING] = jv.y;
+                    re[(FV + 2) * RING] = jv.z;
                 }
             }
             wp += __popcll(m);
             wave_sync();
             while (wp - rp >= 64) {
-                eval(rp, 8, 64);
+                eval.template operator()<true>(rp, 64);
                 rp += 64;
+                wave_sync();
             }
         }
     };
@@ -326,8 +481,8 @@ __global__ void __launch_bounds__(64 * PW) k_pair(const SegDev* __restrict__ seg
             dyc -= Ly * rintf(dyc / Ly);
             const float gx = fmaxf(0.0f, fabsf(dxc) - 0.5f * cwx - bhx);
             const float gy = fmaxf(0.0f, fabsf(dyc) - 0.5f * cwy - bhy);
+            const int col = jxc * ncy + jyc;
             if (gx * gx + gy * gy < rcs2) {
-                const int col = jxc * ncy + jyc;
                 const int base = colstart[col];
                 const int* bo = binoff + (size_t)col * (nzb + 1);
                 const int cnt = bo[nzb];
@@ -344,6 +499,10 @@ __global__ void __launch_bounds__(64 * PW) k_pair(const SegDev* __restrict__ seg
                         b0 = base >> 3;
                         b1 = (base + bo[zb1 + 1] + 7) >> 3;
                         if (b1 > a0) b1 = a0;  // never list a cluster twice
+                    }
+                    if (N3) {  // only clusters after the own one
+                        a0 = max(a0, c + 1);
+                        b0 = max(b0, c + 1);
                     }
                     if (a1 < a0) a1 = a0;
                     if (b1 < b0) b1 = b0;
@@ -373,10 +532,7 @@ __global__ void __launch_bounds__(64 * PW) k_pair(const SegDev* __restrict__ seg
         }
     }
     // ---- remaining ring entries ---------------------------------------------------
-    {
-        const int n = wp - rp;
-        if (n > 0) eval(rp, (n + 7) >> 3, n);
-    }
+    if (wp - rp > 0) eval.template operator()<false>(rp, wp - rp);
 
     // ---- reduce over the 8 j lanes of each i atom and store ------------------------
 #pragma unroll
@@ -385,50 +541,96 @@ __global__ void __launch_bounds__(64 * PW) k_pair(const SegDev* __restrict__ seg
         ay += __shfl_xor(ay, m, 64);
         az += __shfl_xor(az, m, 64);
     }
-    if (jslot == 0 && vi) {
-        const int oi = wsp<const int>(ws, sg->o_orig)[(size_t)b * S + si];
-        size_t o = sg->o_f32;
-        if (MODE == 1 || outsel == 1) o = sg->o_hv32;
-        else if (outsel == 2) o = sg->o_f32m;
-        wsp<float4>(ws, o)[(size_t)b * Q + oi] = make_float4(ax, ay, az, 0.0f);
+    if (jslot == 0 && I.v) {
+        if (N3) {
+            unsafeAtomicAdd(fsx + si, ax);
+            unsafeAtomicAdd(fsy + si, ay);
+            unsafeAtomicAdd(fsz + si, az);
+        } else {
+            const int oi = wsp<const int>(ws, sg->o_orig)[(size_t)b * S + si];
+            size_t o = sg->o_f32;
+            if (MODE == 1 || outsel == 1) o = sg->o_hv32;
+            else if (outsel == 2) o = sg->o_f32m;
+            wsp<float4>(ws, o)[(size_t)b * Q + oi] = make_float4(ax, ay, az, 0.0f);
+        }
     }
     if (wantE) {
+        eacc64 += (double)eacc;
 #pragma unroll
-        for (int m = 1; m < 64; m <<= 1) eacc += __shfl_xor(eacc, m, 64);
-        if (lane == 0) wsp<double>(ws, sg->o_epart)[(size_t)b * cpb + c] = eacc;
+        for (int m = 1; m < 64; m <<= 1) eacc64 += __shfl_xor(eacc64, m, 64);
+        if (lane == 0) wsp<double>(ws, sg->o_epart)[(size_t)b * cpb + c] = eacc64;
     }
 }
 
-template <int MODE, int PW>
+// Slot-order sums of the Newton-3 kernel to original atom order (float4), clearing the
+// slot-order buffer for the next pass.
+__global__ void __launch_bounds__(EWB) k_unsort(const SegDev* __restrict__ segs, Launch L, char* ws,
+                                                int outsel) {
+    const int blk = blockIdx.x;
+    const int p = find_seg(L, blk);
+    const SegDev& sg = segs[p];
+    const int local = blk - L.pf[p];
+    const int b = local / sg.bpb;
+    const int i = (local - b * sg.bpb) * EWB + threadIdx.x;
+    const int Q = sg.s.Q, S = sg.s.S;
+    if (i >= Q) return;
+    const int slot = wsp<const int>(ws, sg.o_slotof)[(size_t)b * Q + i];
+    float* f = wsp<float>(ws, sg.o_fs) + (size_t)b * 3 * S + slot;
+    const float4 v = make_float4(f[0], f[S], f[2 * S], 0.0f);
+    f[0] = 0.0f;
+    f[S] = 0.0f;
+    f[2 * S] = 0.0f;
+    size_t o = sg.o_f32;
+    if (outsel == 1) o = sg.o_hv32;
+    else if (outsel == 2) o = sg.o_f32m;
+    wsp<float4>(ws, o)[(size_t)b * Q + i] = v;
+}
+
+template <int MODE, int PW, int N3>
 static void launch_pair_t(const SegDev* dsegs, const SegDev* hsegs, const Launch& base, char* ws,
                           int outsel, int energy_bead, hipStream_t st) {
     Launch L = base;
     L.pf[0] = 0;
-    for (int p = 0; p < base.nseg; ++p)
+    L.ntmax = 1;
+    for (int p = 0; p < base.nseg; ++p) {
         L.pf[p + 1] = L.pf[p] + (base.nb[p] * hsegs[p].s.cpb + PW - 1) / PW;
+        L.ntmax = std::max(L.ntmax, hsegs[p].s.nt);
+    }
     const int nblk = L.pf[base.nseg];
     if (nblk == 0) return;
     const int grid = ((nblk + 7) / 8) * 8;
-    hipLaunchKernelGGL((k_pair<MODE, PW>), dim3(grid), dim3(64 * PW), 0, st, dsegs, L, ws, outsel,
-                       energy_bead);
+    const size_t lds = 2 * (size_t)L.ntmax * L.ntmax * sizeof(float4) +
+                       (size_t)PW * Fields<MODE, N3>::NF * RING * sizeof(float) +
+                       (size_t)PW * CLIST * sizeof(int);
+    hipLaunchKernelGGL((k_pair<MODE, PW, N3>), dim3(grid), dim3(64 * PW), lds, st, dsegs, L, ws,
+                       outsel, energy_bead);
+}
+
+template <int MODE, int N3>
+static void launch_pair_w(const SegDev* dsegs, const SegDev* hsegs, const Launch& base, char* ws,
+                          int outsel, int energy_bead, int waves, hipStream_t st) {
+    switch (waves) {
+        case 1: launch_pair_t<MODE, 1, N3>(dsegs, hsegs, base, ws, outsel, energy_bead, st); break;
+        case 2: launch_pair_t<MODE, 2, N3>(dsegs, hsegs, base, ws, outsel, energy_bead, st); break;
+        case 8: launch_pair_t<MODE, 8, N3>(dsegs, hsegs, base, ws, outsel, energy_bead, st); break;
+        default: launch_pair_t<MODE, 4, N3>(dsegs, hsegs, base, ws, outsel, energy_bead, st); break;
+    }
 }
 
 void run_pair(const SegDev* dsegs, const SegDev* hsegs, const Launch& base, char* ws, int mode,
-              int outsel, int energy_bead, int waves, hipStream_t st) {
-    if (mode == 0) {
-        switch (waves) {
-            case 1: launch_pair_t<0, 1>(dsegs, hsegs, base, ws, outsel, energy_bead, st); break;
-            case 2: launch_pair_t<0, 2>(dsegs, hsegs, base, ws, outsel, energy_bead, st); break;
-            case 8: launch_pair_t<0, 8>(dsegs, hsegs, base, ws, outsel, energy_bead, st); break;
-            default: launch_pair_t<0, 4>(dsegs, hsegs, base, ws, outsel, energy_bead, st); break;
-        }
+              int outsel, int energy_bead, int waves, int newton3, hipStream_t st) {
+    if (mode == 1) outsel = 1;
+    if (newton3) {
+        if (mode == 0) launch_pair_w<0, 1>(dsegs, hsegs, base, ws, outsel, energy_bead, waves, st);
+        else launch_pair_w<1, 1>(dsegs, hsegs, base, ws, outsel, energy_bead, waves, st);
+        Launch L = base;
+        L.pf[0] = 0;
+        for (int p = 0; p < base.nseg; ++p) L.pf[p + 1] = L.pf[p] + base.nb[p] * hsegs[p].bpb;
+        if (L.pf[base.nseg] > 0)
+            hipLaunchKernelGGL(k_unsort, dim3(L.pf[base.nseg]), dim3(EWB), 0, st, dsegs, L, ws, outsel);
     } else {
-        switch (waves) {
-            case 1: launch_pair_t<1, 1>(dsegs, hsegs, base, ws, outsel, energy_bead, st); break;
-            case 2: launch_pair_t<1, 2>(dsegs, hsegs, base, ws, outsel, energy_bead, st); break;
-            case 8: launch_pair_t<1, 8>(dsegs, hsegs, base, ws, outsel, energy_bead, st); break;
-            default: launch_pair_t<1, 4>(dsegs, hsegs, base, ws, outsel, energy_bead, st); break;
-        }
+        if (mode == 0) launch_pair_w<0, 0>(dsegs, hsegs, base, ws, outsel, energy_bead, waves, st);
+        else launch_pair_w<1, 0>(dsegs, hsegs, base, ws, outsel, energy_bead, waves, st);
     }
 }
 

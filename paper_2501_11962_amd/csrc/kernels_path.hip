@@ -34,7 +34,7 @@ __global__ void __launch_bounds__(EWB) k_resid(const SegDev* __restrict__ segs, 
     const int i = bi * EWB + threadIdx.x;
     const int Q = s.Q, N = L.N[p];
     char* ws = cp.ws;
-    double es = 0.0, eb = 0.0;
+    double es = 0.0, eb = 0.0, d2max = 0.0;
     if (i < Q) {
         const double* Rn = cp.R + sg.roff + (size_t)n * Q * 3;
         const float4 fp = wsp<const float4>(ws, sg.o_f32)[(size_t)n * Q + i];
@@ -56,19 +56,22 @@ __global__ void __launch_bounds__(EWB) k_resid(const SegDev* __restrict__ segs, 
             const double d2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
             es = 0.5 * Ki * d2;
             if (!finite3(d[0], d[1], d[2])) flag(cp.status, ST_NONFINITE);
-            else
-                atomicMax(wsp<unsigned long long>(ws, sg.o_dmax) + n,
-                          (unsigned long long)__double_as_longlong(d2));
+            else d2max = d2;
         } else if (!finite3(f[0], f[1], f[2])) {
             flag(cp.status, ST_NONFINITE);
         }
     }
     const double ses = block_sum(es, sh);
     const double seb = block_sum(eb, sh);
+    const double smax = block_max(d2max, sh);
     if (threadIdx.x == 0) {
         double* rp = wsp<double>(ws, sg.o_rpart) + 2 * ((size_t)n * sg.bpb + bi);
         rp[0] = ses;
         rp[1] = seb;
+        // non-negative doubles order like their bit patterns
+        if (n < N - 1)
+            atomicMax(wsp<unsigned long long>(ws, sg.o_dmax) + n,
+                      (unsigned long long)__double_as_longlong(smax));
     }
 }
 
@@ -128,7 +131,7 @@ __global__ void __launch_bounds__(EWB) k_assemble(const SegDev* __restrict__ seg
     if (!finite3(g[0], g[1], g[2])) flag(cp.status, ST_NONFINITE);
 }
 
-// Sum of pair-energy partials of bead b (each pair counted from both sides).
+// Sum of the per-cluster pair-energy partials of bead b (weights applied in the kernel).
 __device__ double pair_energy_of_bead(const SegDev& sg, char* ws, int b, int t0, int stride) {
     const int ncol = sg.s.ncol;
     const int nslots = wsp<const int>(ws, sg.o_colstart)[(size_t)b * (ncol + 1) + ncol];
@@ -136,7 +139,7 @@ __device__ double pair_energy_of_bead(const SegDev& sg, char* ws, int b, int t0,
     const double* ep = wsp<const double>(ws, sg.o_epart) + (size_t)b * sg.s.cpb;
     double e = 0.0;
     for (int c = t0; c < ncl; c += stride) e += ep[c];
-    return 0.5 * e;
+    return e;
 }
 
 // One block per path: V_eff = U(R^1) + E_spring.

@@ -41,6 +41,7 @@ struct mop_plan_s {
     mop_system sys;
     int max_beads;
     int waves;
+    int newton3;
     SegDev hseg;          // single-path layout (capacity max_beads)
     SegDev* dseg;
     size_t ws_bytes;
@@ -50,6 +51,7 @@ struct mop_batch_s {
     mop_ctx ctx;
     int P;
     int waves;
+    int newton3;
     std::vector<int> N;
     std::vector<SegDev> hsegs;
     SegDev* dsegs;
@@ -181,6 +183,7 @@ static size_t layout(SegDev& sg, int maxb, int maxN, size_t base) {
     take(sg.o_colcnt, B * nc * 4);
     take(sg.o_colstart, B * (nc + 1) * 4);
     take(sg.o_vs, B * S * 16);
+    take(sg.o_fs, B * S * 12);
     take(sg.o_f32, B * Q * 16);
     take(sg.o_f32m, B * Q * 16);
     take(sg.o_hv32, B * Q * 16);
@@ -196,7 +199,7 @@ static size_t layout(SegDev& sg, int maxb, int maxN, size_t base) {
 
 static SysDev plan_geometry(const mop_system_s* sys, const mop_plan_opts* opts) {
     SysDev s = sys->dev;
-    const double cwt = (opts && opts->col_width > 0.0) ? opts->col_width : 0.5;
+    const double cwt = (opts && opts->col_width > 0.0) ? opts->col_width : 0.4;
     const double zbt = (opts && opts->zbin > 0.0) ? opts->zbin : 0.1;
     const double* L = sys->box;
     s.ncx = std::max(1, (int)std::floor(L[0] / cwt));
@@ -400,6 +403,7 @@ int mop_plan_create(mop_system sys, int32_t max_beads, const mop_plan_opts* opts
     pl->sys = sys;
     pl->max_beads = max_beads;
     pl->waves = waves;
+    pl->newton3 = (opts && (opts->flags & MOP_PLAN_NEWTON3)) ? 1 : 0;
     base_seg(pl->hseg, plan_geometry(sys, opts));
     pl->hseg.roff = 0;
     pl->hseg.vidx = 0;
@@ -472,7 +476,7 @@ int bead_forces(mop_plan plan, const double* R, int32_t B, float* F, double* U, 
     cp.Uout = U;
     const Launch L = one_path(B, B);
     run_binning(plan->dseg, &plan->hseg, L, cp.ws, R, 0, 0.0, st);
-    run_pair(plan->dseg, &plan->hseg, L, cp.ws, 0, 0, U ? -2 : -1, plan->waves, st);
+    run_pair(plan->dseg, &plan->hseg, L, cp.ws, 0, 0, U ? -2 : -1, plan->waves, plan->newton3, st);
     run_finalize_forces(plan->dseg, &plan->hseg, L, cp, st);
     return finish(plan->sys->ctx);
 }
@@ -489,7 +493,7 @@ int bead_hvp(mop_plan plan, const double* R, const double* V, int32_t B, float* 
     const Launch L = one_path(B, B);
     run_binning(plan->dseg, &plan->hseg, L, cp.ws, R, 0, 0.0, st);
     run_prep_v(plan->dseg, &plan->hseg, L, cp, st);
-    run_pair(plan->dseg, &plan->hseg, L, cp.ws, 1, 0, -1, plan->waves, st);
+    run_pair(plan->dseg, &plan->hseg, L, cp.ws, 1, 0, -1, plan->waves, plan->newton3, st);
     run_finalize_hvp(plan->dseg, &plan->hseg, L, cp, st);
     return finish(plan->sys->ctx);
 }
@@ -497,8 +501,8 @@ int bead_hvp(mop_plan plan, const double* R, const double* V, int32_t B, float* 
 // The phases of V_eff and its gradient over every path of `base`.  ev, when given,
 // receives an event after each phase (MOP_NPHASES + 1 events, ev[0] at the start).
 static void path_sequence(const SegDev* dsegs, const SegDev* hsegs, const Launch& base,
-                          const CallPtrs& cp, bool grad, int mode, int waves, hipStream_t st,
-                          hipEvent_t* ev = nullptr) {
+                          const CallPtrs& cp, bool grad, int mode, int waves, int n3,
+                          hipStream_t st, hipEvent_t* ev = nullptr) {
     auto mark = [&](int k) {
         if (ev) (void)hipEventRecord(ev[k], st);
     };
@@ -506,7 +510,7 @@ static void path_sequence(const SegDev* dsegs, const SegDev* hsegs, const Launch
     // forces of beads 1..N-1 (bead 1 alone for N = 1), energy of bead 1
     run_binning(dsegs, hsegs, base, cp.ws, cp.R, 0, 0.0, st);
     mark(1);
-    run_pair(dsegs, hsegs, base, cp.ws, 0, 0, 0, waves, st);
+    run_pair(dsegs, hsegs, base, cp.ws, 0, 0, 0, waves, n3, st);
     mark(2);
     run_resid(dsegs, hsegs, base, cp, st);
     mark(3);
@@ -517,13 +521,13 @@ static void path_sequence(const SegDev* dsegs, const SegDev* hsegs, const Launch
             Lh.nb[p] = base.N[p] - 1;
             any = any || Lh.nb[p] > 0;
         }
-        if (any && mode == 0) run_pair(dsegs, hsegs, Lh, cp.ws, 1, 0, -1, waves, st);
+        if (any && mode == 0) run_pair(dsegs, hsegs, Lh, cp.ws, 1, 0, -1, waves, n3, st);
         mark(4);
         if (any && mode == 1) {
             run_binning(dsegs, hsegs, Lh, cp.ws, cp.R, +1, cp.fd_h, st);
-            run_pair(dsegs, hsegs, Lh, cp.ws, 0, 1, -1, waves, st);
+            run_pair(dsegs, hsegs, Lh, cp.ws, 0, 1, -1, waves, n3, st);
             run_binning(dsegs, hsegs, Lh, cp.ws, cp.R, -1, cp.fd_h, st);
-            run_pair(dsegs, hsegs, Lh, cp.ws, 0, 2, -1, waves, st);
+            run_pair(dsegs, hsegs, Lh, cp.ws, 0, 2, -1, waves, n3, st);
         }
         mark(5);
         run_assemble(dsegs, hsegs, base, cp, mode, st);
@@ -546,7 +550,8 @@ int veff_energy(mop_plan plan, const double* R, int32_t N, double* veff, double*
     cp.u1 = u1;
     cp.espring = espring;
     const Launch L = one_path(N, N > 1 ? N - 1 : 1);
-    path_sequence(plan->dseg, &plan->hseg, L, cp, false, 0, plan->waves, plan->sys->ctx->stream);
+    path_sequence(plan->dseg, &plan->hseg, L, cp, false, 0, plan->waves, plan->newton3,
+                  plan->sys->ctx->stream);
     return finish(plan->sys->ctx);
 }
 
@@ -562,7 +567,8 @@ int veff_grad(mop_plan plan, const double* R, int32_t N, double* G, double* veff
     cp.veff = veff;
     cp.fd_h = fd_h;
     const Launch L = one_path(N, N > 1 ? N - 1 : 1);
-    path_sequence(plan->dseg, &plan->hseg, L, cp, true, mode, plan->waves, plan->sys->ctx->stream);
+    path_sequence(plan->dseg, &plan->hseg, L, cp, true, mode, plan->waves, plan->newton3,
+                  plan->sys->ctx->stream);
     return finish(plan->sys->ctx);
 }
 
@@ -582,7 +588,7 @@ int veff_grad_timed(mop_plan plan, const double* R, int32_t N, double* G, double
     cp.veff = veff;
     cp.fd_h = fd_h;
     const Launch L = one_path(N, N > 1 ? N - 1 : 1);
-    path_sequence(plan->dseg, &plan->hseg, L, cp, true, mode, plan->waves, st, ev);
+    path_sequence(plan->dseg, &plan->hseg, L, cp, true, mode, plan->waves, plan->newton3, st, ev);
     int rc = finish(plan->sys->ctx);
     if (hipEventSynchronize(ev[MOP_NPHASES]) != hipSuccess) rc = MOP_EHIP;
     for (int k = 0; k < MOP_NPHASES; ++k) {
@@ -610,6 +616,7 @@ int mop_batch_create(int32_t P, const mop_plan* plans, const int32_t* N, mop_bat
     bt->ctx = ctx;
     bt->P = P;
     bt->waves = plans[0]->waves;
+    bt->newton3 = plans[0]->newton3;
     bt->N.assign(N, N + P);
     bt->hsegs.resize(P);
     size_t off = 256;
@@ -665,7 +672,8 @@ int mop_batch_veff_grad(mop_batch batch, const double* R, double* G, double* vef
         L.N[p] = batch->N[p];
         L.nb[p] = batch->N[p] > 1 ? batch->N[p] - 1 : 1;
     }
-    path_sequence(batch->dsegs, batch->hsegs.data(), L, cp, true, mode, batch->waves, batch->ctx->stream);
+    path_sequence(batch->dsegs, batch->hsegs.data(), L, cp, true, mode, batch->waves,
+                  batch->newton3, batch->ctx->stream);
     return finish(batch->ctx);
 }
 

@@ -9,6 +9,7 @@
 //     umeta int2   {exclusion key, LJ type}
 //     orig  int    atom index of the slot (-1 for padding)
 //     vs    float4 the vector of a Hessian-vector product, slot order
+//     fs    float  x3 pair sums in slot order (structure of arrays), Newton-3 kernels
 //   Per atom (original order): slotof, pair force / pair HVP outputs (float4).
 // Per path: FP64 residuals d^n [(N-1)][Q][3], reduction partials, per-bead max |d|^2.
 #pragma once
@@ -74,13 +75,14 @@ struct SegDev {
     int vidx;             // index of this path's scalar outputs
     int bpb;              // elementwise blocks per bead: ceil(Q / EWB)
     size_t o_upos, o_umeta, o_orig, o_slotof, o_atomu, o_rank, o_bincnt, o_binoff,
-        o_colcnt, o_colstart, o_vs, o_f32, o_f32m, o_hv32, o_epart, o_d64, o_rpart,
+        o_colcnt, o_colstart, o_vs, o_fs, o_f32, o_f32m, o_hv32, o_epart, o_d64, o_rpart,
         o_dmax, o_eres;
 };
 
 // Per-launch description, passed by value.
 struct Launch {
     int nseg;
+    int ntmax;            // largest LJ type count of the launch (pair kernels)
     int pf[MAXSEG + 1];   // block prefix per segment
     int N[MAXSEG];        // beads of each path in this call
     int nb[MAXSEG];       // pair beads of each path in this call

@@ -243,7 +243,7 @@ def test_autograd_function(mop, ctx):
     # two calls may sum FP32 pair terms in a different order (atomic bin ranks)
     scale = float(G.abs().max())
     assert torch.allclose(Rt.grad, 2.5 * G, rtol=1e-5, atol=1e-6 * scale)
-    assert abs(float(v) - float(v2[0])) < 1e-9 * abs(float(v2[0]))
+    assert abs(float(v) - float(v2[0])) < 1e-7 * abs(float(v2[0]))
 
 
 def test_gpu_invariants(mop, ctx):
@@ -276,3 +276,58 @@ def test_cfg3_parity(cfg, N, mop, ctx, cl_oracle):
     say(f"   G relL2 {errs}  V_eff rel {abs(float(v[0]) - vo) / abs(vo):.2e}")
     assert max(errs) < TOL_G
     assert abs(float(v[0]) - vo) < TOL_V * abs(vo)
+
+
+@pytest.mark.parametrize("name,N", [("cfg1", 4), ("cfg2", 4)])
+def test_newton3_mode(name, N, mop, ctx):
+    """Newton's-third-law variant (atomics) gives the same gradient."""
+    s = SMALL[name]()
+    R, _, _ = W.random_walk_path(s, N, 17, 0.005 if name == "cfg1" else None)
+    plan = mop.Plan(mop.System(ctx, s), N, newton3=True)
+    G, v = mop.veff_grad(plan, cuda(R))
+    Go, vo = OP.veff_grad(Model(s), R)
+    G = G.cpu().numpy()
+    errs = [rel(G[n], Go[n]) for n in range(N)]
+    say(f"[newton3] {name} G relL2 max {max(errs):.2e}")
+    assert max(errs) < TOL_G
+    assert abs(float(v[0]) - vo) < TOL_V * abs(vo)
+    # run to run: summation order differs, well below the tolerance
+    G2, _ = mop.veff_grad(plan, cuda(R))
+    assert rel(G2.cpu().numpy(), G) < 1e-6
+
+
+def test_graph_replay_matches_eager(mop, ctx):
+    """The whole veff_grad call captured once and replayed; each replay checked against
+    an eager call, with eager work and synchronisation between replays."""
+    import torch
+    s = W.cfg2()
+    N = 6
+    R, _, _ = W.random_walk_path(s, N, 23)
+    plan = mop.Plan(mop.System(ctx, s), N)
+    Rt = cuda(R)
+    G = torch.empty_like(Rt)
+    v = torch.empty(1, dtype=torch.float64, device=Rt.device)
+    mop.veff_grad(plan, Rt, 0, 0.0, G, v)  # warm-up outside capture
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    cs = torch.cuda.Stream()
+    cs.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.graph(g, stream=cs):
+        ctx.set_stream()
+        mop.veff_grad(plan, Rt, 0, 0.0, G, v)
+    ctx.set_stream()
+    torch.cuda.synchronize()
+    Go, vo = OP.veff_grad(Model(s), R)
+    for k in range(4):
+        # eager work on the same workspace between replays (different input)
+        Rk = Rt + 1e-3 * (k + 1)
+        mop.veff_grad(plan, Rk)
+        torch.cuda.synchronize()
+        G.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        e = rel(G.cpu().numpy(), Go)
+        say(f"[graph] replay {k}: G relL2 {e:.2e}, V_eff rel {abs(float(v[0]) - vo) / abs(vo):.2e}")
+        assert e < TOL_G
+        assert abs(float(v[0]) - vo) < TOL_V * abs(vo)
+    assert plan.status() == 0
