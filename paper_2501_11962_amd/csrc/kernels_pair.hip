@@ -209,7 +209,9 @@ __global__ void __launch_bounds__(64 * PW) k_pair(const SegDev* __restrict__ seg
     const int si = c * CLUSTER + isub;
     const uint4 ui = upos[si];
     const int2 mi = umeta[si];
-    const uint4 ref = upos[c * CLUSTER];
+    // first reference point: the cluster's middle atom (atoms of a cluster are z-sorted
+    // inside one column)
+    const uint4 ref = upos[c * CLUSTER + 3];
     IAtom I;
     I.v = mi.x != DUMMY_KEY;
     I.q = __uint_as_float(ui.w);
@@ -226,7 +228,7 @@ __global__ void __launch_bounds__(64 * PW) k_pair(const SegDev* __restrict__ seg
         I.vy = v4.y;
         I.vz = v4.z;
     }
-    // bounding box relative to the first atom, then re-referenced to its centre uc
+    // bounding box relative to the reference atom, then to its own centre
     float lox, hix, loy, hiy, loz, hiz;
     auto bbox = [&](float x, float y, float z) {
         lox = I.v ? x : 3.0e38f;
@@ -247,19 +249,34 @@ __global__ void __launch_bounds__(64 * PW) k_pair(const SegDev* __restrict__ seg
     };
     bbox((float)(int)(ui.x - ref.x) * sx, (float)(int)(ui.y - ref.y) * sy,
          (float)(int)(ui.z - ref.z) * sz);
-    const uint32_t ucx = ref.x + (uint32_t)(long long)rintf(0.5f * (lox + hix) / sx);
-    const uint32_t ucy = ref.y + (uint32_t)(long long)rintf(0.5f * (loy + hiy) / sy);
-    const uint32_t ucz = ref.z + (uint32_t)(long long)rintf(0.5f * (loz + hiz) / sz);
+    // re-reference to the box centre uc: the image of an atom nearest the centre is the
+    // one nearest the box, which keeps the candidate test conservative in small boxes.
+    // The shifted bounds may differ from the atoms' new coordinates by an ulp, which the
+    // search-radius margin absorbs.
+    const int ocx = (int)rintf(0.5f * (lox + hix) / sx);
+    const int ocy = (int)rintf(0.5f * (loy + hiy) / sy);
+    const int ocz = (int)rintf(0.5f * (loz + hiz) / sz);
+    const uint32_t ucx = ref.x + (uint32_t)ocx, ucy = ref.y + (uint32_t)ocy, ucz = ref.z + (uint32_t)ocz;
+    {
+        const float fx = (float)ocx * sx, fy = (float)ocy * sy, fz = (float)ocz * sz;
+        lox -= fx;
+        hix -= fx;
+        loy -= fy;
+        hiy -= fy;
+        loz -= fz;
+        hiz -= fz;
+    }
     I.x = (float)(int)(ui.x - ucx) * sx;
     I.y = (float)(int)(ui.y - ucy) * sy;
     I.z = (float)(int)(ui.z - ucz) * sz;
-    bbox(I.x, I.y, I.z);
-    // Coordinates relative to the centre give exact pair differences when
-    // extent + search radius < L/2 along every axis; otherwise each pair difference is
-    // taken from the fixed-point coordinates (small boxes, sparse columns).
-    const bool exact = (hix - lox + rcs >= 0.5f * sg->s.Lf[0]) ||
-                       (hiy - loy + rcs >= 0.5f * sg->s.Lf[1]) ||
-                       (hiz - loz + rcs >= 0.5f * sg->s.Lf[2]);
+    // Coordinates relative to the reference give exact pair differences when
+    // max(|lo|, |hi|) + search radius < L/2 along every axis: for a pair within the
+    // cutoff, (image of i) + d then lies within L/2 of the reference, so it is the image
+    // of j that the relative coordinate picks.  Otherwise each pair difference is taken
+    // from the fixed-point coordinates (small boxes, sparse columns).
+    const bool exact = (fmaxf(-lox, hix) + rcs >= 0.5f * sg->s.Lf[0]) ||
+                       (fmaxf(-loy, hiy) + rcs >= 0.5f * sg->s.Lf[1]) ||
+                       (fmaxf(-loz, hiz) + rcs >= 0.5f * sg->s.Lf[2]);
     const int cx = fixed_bin(ref.x, ncx), cy = fixed_bin(ref.y, ncy);
 
     // z window of candidate atoms, in z bins
@@ -289,12 +306,6 @@ __global__ void __launch_bounds__(64 * PW) k_pair(const SegDev* __restrict__ seg
 
     float* ring = s_ring + wave * NF * RING;
     int* clist = s_cl + wave * CLIST;
-    // Ring entries past the valid count are read by the last step of an evaluation and
-    // masked by a select on g and h; masked products are still formed (0 * dx, 0 * dv),
-    // so every field such an entry can feed must hold a finite value, and the type
-    // field a valid table index: clear the ring once.
-    for (int e = lane; e < NF * RING; e += 64) ring[e] = 0.0f;
-    wave_sync();
 
     // ---- own cluster (N3): one 8 x 8 block, both sides, weight 1/2 for energies ----
     if (N3) {
@@ -357,9 +368,27 @@ __global__ void __launch_bounds__(64 * PW) k_pair(const SegDev* __restrict__ seg
                 vjy = rb[(FV + 1) * RING + o];
                 vjz = rb[(FV + 2) * RING + o];
             }
+            const bool valid = FULL || o + jslot < count;
+            // Entries past the count of a partial chunk may hold anything (never written
+            // in this wave's lifetime): masked products are still formed (0 * dx, 0 * dv),
+            // so give them finite operands and a valid table index.
+            float jxv = jx, jyv = jy, jzv = jz, qjv = qj;
+            int tjv = tj;
+            if (!FULL) {
+                jxv = valid ? jx : 0.0f;
+                jyv = valid ? jy : 0.0f;
+                jzv = valid ? jz : 0.0f;
+                qjv = valid ? qj : 0.0f;
+                tjv = valid ? tj : 0;
+                if (MODE == 1) {
+                    vjx = valid ? vjx : 0.0f;
+                    vjy = valid ? vjy : 0.0f;
+                    vjz = valid ? vjz : 0.0f;
+                }
+            }
             float tx, ty, tz, en = 0.f;
-            pair_term<MODE, EX, WE, N3 == 1>(I, P, tabrow, jx, jy, jz, qj, kj, tj, vjx, vjy, vjz,
-                                             FULL || o + jslot < count, ax, ay, az, tx, ty, tz, en);
+            pair_term<MODE, EX, WE, N3 == 1>(I, P, tabrow, jxv, jyv, jzv, qjv, kj, tjv, vjx, vjy,
+                                             vjz, valid, ax, ay, az, tx, ty, tz, en);
             if (WE) eacc += N3 ? en : 0.5f * en;
             if (N3) {
                 __hip_atomic_fetch_add(rb + (F_J + 0) * RING + o, tx, __ATOMIC_RELAXED,
@@ -398,34 +427,45 @@ __global__ void __launch_bounds__(64 * PW) k_pair(const SegDev* __restrict__ seg
     };
 
     // ---- candidate clusters [0, T) of clist --------------------------------------
+    // Candidate atoms are loaded one chunk (8 clusters) ahead of their use, so the
+    // global-load latency of chunk q+1 overlaps the tests, ring writes and pair
+    // evaluations of chunk q.
     auto process = [&](int T) {
+        const uint4 z4 = make_uint4(0u, 0u, 0u, 0u);
+        int nslot = (lane >> 3) < T ? clist[lane >> 3] * CLUSTER + (lane & 7) : -1;
+        uint4 nuj = nslot >= 0 ? upos[nslot] : z4;
+        int2 nmj = nslot >= 0 ? umeta[nslot] : make_int2(DUMMY_KEY, 0);
+        float4 njv = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (MODE == 1 && nslot >= 0) njv = vs[nslot];
         for (int q = 0; q < T; q += 8) {
-            const int ci = q + (lane >> 3);
-            bool pass = false;
-            float jx = 0.f, jy = 0.f, jz = 0.f, jq = 0.f;
-            int jk = 0, jt = 0, slot = 0;
-            float4 jv = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (ci < T) {
-                slot = clist[ci] * CLUSTER + (lane & 7);
-                const uint4 uj = upos[slot];
-                const int2 mj = umeta[slot];
-                if (MODE == 1) jv = vs[slot];
-                jx = (float)(int)(uj.x - ucx) * sx;
-                jy = (float)(int)(uj.y - ucy) * sy;
-                jz = (float)(int)(uj.z - ucz) * sz;
-                const float ex = fmaxf(fmaxf(lox - jx, jx - hix), 0.0f);
-                const float ey = fmaxf(fmaxf(loy - jy, jy - hiy), 0.0f);
-                const float ez = fmaxf(fmaxf(loz - jz, jz - hiz), 0.0f);
-                pass = (mj.x != DUMMY_KEY) & (fmaf(ex, ex, fmaf(ey, ey, ez * ez)) < rcs2);
-                if (exact) {
-                    jx = __uint_as_float(uj.x);
-                    jy = __uint_as_float(uj.y);
-                    jz = __uint_as_float(uj.z);
+            const int slot = nslot;
+            const uint4 uj = nuj;
+            const int2 mj = nmj;
+            const float4 jv = njv;
+            {
+                const int cn = q + 8 + (lane >> 3);
+                nslot = cn < T ? clist[cn] * CLUSTER + (lane & 7) : -1;
+                if (nslot >= 0) {
+                    nuj = upos[nslot];
+                    nmj = umeta[nslot];
+                    if (MODE == 1) njv = vs[nslot];
                 }
-                jq = __uint_as_float(uj.w);
-                jk = mj.x;
-                jt = mj.y;
             }
+            float jx = (float)(int)(uj.x - ucx) * sx;
+            float jy = (float)(int)(uj.y - ucy) * sy;
+            float jz = (float)(int)(uj.z - ucz) * sz;
+            const float ex = fmaxf(fmaxf(lox - jx, jx - hix), 0.0f);
+            const float ey = fmaxf(fmaxf(loy - jy, jy - hiy), 0.0f);
+            const float ez = fmaxf(fmaxf(loz - jz, jz - hiz), 0.0f);
+            const bool pass = (slot >= 0) & (mj.x != DUMMY_KEY) &
+                              (fmaf(ex, ex, fmaf(ey, ey, ez * ez)) < rcs2);
+            if (exact) {
+                jx = __uint_as_float(uj.x);
+                jy = __uint_as_float(uj.y);
+                jz = __uint_as_float(uj.z);
+            }
+            const float jq = __uint_as_float(uj.w);
+            const int jk = mj.x, jt = mj.y;
             const unsigned long long m = __ballot(pass);
             const int off = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
                                                       __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));

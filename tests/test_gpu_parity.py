@@ -331,3 +331,55 @@ def test_graph_replay_matches_eager(mop, ctx):
         assert e < TOL_G
         assert abs(float(v[0]) - vo) < TOL_V * abs(vo)
     assert plan.status() == 0
+
+
+@pytest.mark.parametrize("name,N", [("cfg2", 5), ("water300", 5)])
+def test_analytic_beats_fd_accuracy(name, N, mop, ctx, cl_oracle):
+    """Equal-accuracy comparison: the exact HVP path against the FD-HVP path of eq. (5)
+    over a sweep of displacement lengths h; both measured against the FP64 exact G."""
+    s = SMALL[name]()
+    R, _, _ = W.random_walk_path(s, N, 41)
+    plan = mop.Plan(mop.System(ctx, s), N)
+    Go, _ = OP.veff_grad(oracle_model(s, cl_oracle), R)
+    Rt = cuda(R)
+    Ga, _ = mop.veff_grad(plan, Rt)
+    ea = rel(Ga.cpu().numpy(), Go)
+    efd = {}
+    for h in (1e-5, 3e-5, 1e-4, 3e-4, 1e-3):
+        Gf, _ = mop.veff_grad(plan, Rt, mode=1, fd_h=h)
+        efd[h] = rel(Gf.cpu().numpy(), Go)
+    say(f"[accuracy] {name}: analytic relL2 {ea:.2e}; FD " +
+        ", ".join(f"h={h:g}: {e:.2e}" for h, e in efd.items()))
+    assert ea < TOL_G
+    assert ea < min(efd.values())
+
+
+def test_cfg4_full_size_sampled(mop, ctx, cl_oracle):
+    """The benchmark workload (150,000 atoms x 16 beads) in the launch configuration
+    bench.py times: V_eff and the gradient of beads 1, 2 and 16 against the FP64 cell-list
+    oracle; forces of bead 1 through bead_forces."""
+    from oracle import path as OPth
+    s, R = W.make_config("cfg4")
+    N, Q = R.shape[0], s["Q"]
+    plan = mop.Plan(mop.System(ctx, s), N)
+    Rt = cuda(R)
+    G, v = mop.veff_grad(plan, Rt)
+    G = G.cpu().numpy()
+    v = float(v[0])
+    assert plan.status() == 0
+    m = cl_oracle.CellModel(s)
+    c, K = OPth.coefficients(m)
+    F = {n: m.forces(R[n]) for n in range(N - 1)}
+    d = {n: OPth.min_image(R[n + 1] - R[n], m.box) - c[:, None] * F[n] for n in range(N - 1)}
+    vo = m.energy(R[0]) + sum(float(np.sum(0.5 * K[:, None] * d[n] ** 2)) for n in range(N - 1))
+    Go0 = -F[0] - K[:, None] * d[0] + 0.5 * m.hvp(R[0], d[0])
+    Go1 = K[:, None] * d[0] - K[:, None] * d[1] + 0.5 * m.hvp(R[1], d[1])
+    GoN = K[:, None] * d[N - 2]
+    e = [rel(G[0], Go0), rel(G[1], Go1), rel(G[N - 1], GoN)]
+    say(f"[cfg4] G relL2 beads 1, 2, N: {e}; V_eff rel {abs(v - vo) / abs(vo):.2e}")
+    assert max(e) < TOL_G
+    assert abs(v - vo) < TOL_V * abs(vo)
+    Fg, _ = mop.bead_forces(plan, Rt[:1].contiguous(), want_energy=False)
+    ef = rel(Fg.cpu().numpy()[0], F[0])
+    say(f"[cfg4] bead_forces relL2 {ef:.2e}")
+    assert ef < TOL_F
