@@ -35,12 +35,13 @@ __device__ __forceinline__ int fixed_bin(uint32_t u, int n) {
     return static_cast<int>((static_cast<uint64_t>(u) * static_cast<uint64_t>(n)) >> 32);
 }
 
-// Orders the wave's LDS traffic: all earlier LDS accesses of the wave complete before
-// any later one is issued, and the compiler moves no memory access across it.
+// Orders LDS traffic between the lanes of one wave: the compiler moves no memory
+// access across it.  A wave's LDS instructions execute in issue order, so wavefront
+// scope needs no wait for earlier LDS accesses to complete.
 __device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 __device__ __forceinline__ int wave_incl_scan(int v) {

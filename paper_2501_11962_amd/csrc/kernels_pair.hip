@@ -478,8 +478,8 @@ __global__ void __launch_bounds__(64 * PW) k_pair(const SegDev* __restrict__ seg
                 re[F_Q * RING] = jq;
                 re[F_K * RING] = __int_as_float(jk);
                 re[F_T * RING] = __int_as_float(jt);
-                re[F_S * RING] = __int_as_float(slot);
                 if (N3) {
+                    re[F_S * RING] = __int_as_float(slot);
                     re[(F_J + 0) * RING] = 0.0f;
                     re[(F_J + 1) * RING] = 0.0f;
                     re[(F_J + 2) * RING] = 0.0f;
