@@ -34,6 +34,7 @@ PEAK_HBM_GBS = 8000.0
 # counted from the pair formulas with Newton's third law (each pair once).
 FLOP_FORCE_PAIR = 34
 FLOP_HVP_PAIR = 60
+FD_SWEEP = (1e-5, 3e-5, 1e-4, 3e-4, 1e-3)   # FD displacement lengths h (nm)
 PAIR_SRC = os.path.join(ROOT, "paper_2501_11962_amd", "csrc", "kernels_pair.hip")
 
 
@@ -88,13 +89,14 @@ def cpu_baseline(system, R, beads):
     m = cl.CellModel(system)
     sub = np.ascontiguousarray(R[:beads])
     t0 = time.perf_counter()
-    OP.veff_grad(m, sub)
+    Gsub, _ = OP.veff_grad(m, sub)
     dt = time.perf_counter() - t0
+    # beads 1 .. beads-1 of the sub-path carry the same gradient as in the whole path
     return dict(value=system["Q"] * beads / dt, unit="atom·beads/s", cores=cl.max_threads(),
                 kind="oracle",
                 sample=f"veff_grad of the first {beads} beads of the same path "
                        f"({beads - 1} force + {beads - 1} Hessian-vector passes over "
-                       f"{system['Q']} atoms), {dt:.1f} s wall")
+                       f"{system['Q']} atoms), {dt:.1f} s wall"), Gsub[:beads - 1]
 
 
 def main():
@@ -108,6 +110,9 @@ def main():
     ap.add_argument("--no-fd", action="store_true")
     ap.add_argument("--fd-h", type=float, default=1e-4)
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="run one plain device copy of this many MiB first (a known-size "
+                         "kernel that scales HBM byte counters read by a profiler)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (--gpus {args.gpus} requested): this build "
@@ -129,6 +134,14 @@ def main():
     plan = mop.Plan(mop.System(ctx, system), N)
     G = torch.empty_like(Rt)
     v = torch.empty(1, dtype=torch.float64, device=dev)
+    if args.calib_copy_mib > 0:
+        n = args.calib_copy_mib << 18
+        a = torch.ones(n, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        torch.neg(a, out=b)             # reads and writes 4 n bytes each
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy: {4 * n} bytes read, {4 * n} bytes written")
+        del a, b
 
     def step():
         mop.veff_grad(plan, Rt, 0, 0.0, G, v)
@@ -192,8 +205,11 @@ def main():
     phases = {k: acc[k] / args.steps for k in acc}
     log(f"[bench] phases (ms): {json.dumps({k: round(x, 4) for k, x in phases.items()})}")
 
+    Ga_head = G[:max(args.cpu_beads - 1, 1)].cpu().numpy()
+
     # finite-difference comparison path (eq. 5 as printed: 3 force passes per bead)
     fd = None
+    Gfd_head = {}
     if not args.no_fd:
         for _ in range(2):
             mop.veff_grad(plan, Rt, 1, args.fd_h, G, v)
@@ -207,6 +223,9 @@ def main():
         fd = dict(value=Q * N / (ms_fd * 1e-3), ms_per_step=ms_fd, fd_h_nm=args.fd_h,
                   speedup_analytic_over_fd=ms_fd / ms)
         log(f"[bench] FD path: {ms_fd:.3f} ms/step")
+        for h in FD_SWEEP:
+            mop.veff_grad(plan, Rt, 1, h, G, v)
+            Gfd_head[h] = G[:Ga_head.shape[0]].cpu().numpy()
 
     # roofline of the dominant kernel
     npairs = unique_pairs(system, R[0])
@@ -238,8 +257,18 @@ def main():
                roofline=roof, fd=fd, phases_ms=phases)
     if not args.no_cpu_baseline:
         log(f"[bench] CPU oracle on {args.cpu_beads} beads ...")
-        out["cpu_baseline"] = cpu_baseline(system, R, args.cpu_beads)
+        out["cpu_baseline"], Go_head = cpu_baseline(system, R, args.cpu_beads)
         log(f"[bench] CPU oracle: {out['cpu_baseline']['value']:.3e} atom*beads/s")
+
+        def rel(a, b):
+            return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+        acc = dict(reference=f"FP64 oracle gradient of beads 1..{Go_head.shape[0]}",
+                   analytic=rel(Ga_head, Go_head))
+        if Gfd_head:
+            acc["fd_by_h_nm"] = {f"{h:g}": rel(g, Go_head) for h, g in Gfd_head.items()}
+            acc["fd_best"] = min(acc["fd_by_h_nm"].values())
+        out["accuracy_relL2"] = acc
+        log(f"[bench] accuracy: {json.dumps(acc)}")
     print(json.dumps(out), flush=True)
 
 

@@ -172,6 +172,36 @@ int veff_grad(mop_plan plan, const double* R, int32_t N, double* G, double* veff
               int32_t mode, double fd_h, void* ws);
 
 /*
+ * Path molecular dynamics (eq. 4): nsteps steps of the whole polymer R [N][Q][3] under
+ * F_eff = -grad V_eff, with fictitious masses read as the atoms' masses (the same for
+ * every bead).  One step is the splitting B A O A B:
+ *     V -= tau/2 G/M;  R += tau/2 V;  V = c1 V + c2 xi/sqrt(M);  R += tau/2 V;
+ *     G = grad V_eff(R) (exact Hessian-vector products, as veff_grad mode 0);
+ *     V -= tau/2 G/M
+ * with c1 = exp(-gamma tau), c2 = sqrt((1 - c1^2) kT).  gamma = 0 skips the O part:
+ * velocity Verlet, the constant-energy integrator of appendix A.2; gamma > 0 is the
+ * Langevin thermostat of its constant-temperature runs.  xi are standard normal
+ * deviates from Philox4x64-10 (Salmon et al., SC 2011) keyed by (seed, 0) on the
+ * counter (bead * Q + atom, step0 + k, 0, 0), mapped to (0,1) as
+ * (floor(x / 2^12) + 1/2) 2^-52 and through Box-Muller (outputs 0,1 -> x, y; 2,3 -> z).
+ *   R, V   [N][Q][3] device doubles, updated in place (V in nm/ps)
+ *   G      [N][Q][3] device doubles: on entry grad V_eff of the entry R (from
+ *          veff_grad); on exit that of the final R
+ *   energies  device doubles [nsteps][2] = {V_eff, kinetic energy} after each step, or
+ *          NULL
+ *   tau > 0 (ps), gamma >= 0 (1/ps), kT >= 0 (kJ/mol); MOP_EINVAL otherwise.
+ */
+typedef struct {
+    double tau;
+    double gamma;
+    double kT;
+    uint64_t seed;
+} mop_pmd_params;
+int pmd_step(mop_plan plan, double* R, double* V, double* G, int32_t N,
+             const mop_pmd_params* prm, uint64_t step0, int32_t nsteps, double* energies,
+             void* ws);
+
+/*
  * Batch of P independent paths (each with its own plan/system and bead count),
  * evaluated together: every phase of all paths is one kernel launch.  Paths are packed
  * back to back in one buffer: path p occupies N_p*Q_p*3 doubles starting at element

@@ -48,6 +48,11 @@ class _Desc(C.Structure):
     ]
 
 
+class _PmdParams(C.Structure):
+    _fields_ = [("tau", C.c_double), ("gamma", C.c_double), ("kT", C.c_double),
+                ("seed", C.c_uint64)]
+
+
 class _Opts(C.Structure):
     _fields_ = [("col_width", C.c_double), ("zbin", C.c_double), ("waves", C.c_int32),
                 ("flags", C.c_int32)]
@@ -59,7 +64,7 @@ EXPORTS = [
     "mop_workspace_size", "bead_forces", "bead_hvp", "veff_energy", "veff_grad",
     "mop_batch_create", "mop_batch_destroy", "mop_batch_workspace_size",
     "mop_batch_veff_grad", "mop_status", "mop_status_clear", "mop_strerror", "mop_plan_info",
-    "veff_grad_timed",
+    "veff_grad_timed", "pmd_step",
 ]
 PHASES = ["bin", "force", "resid", "hvp", "fd", "assemble"]
 
@@ -96,6 +101,8 @@ def lib():
         "mop_strerror": ([C.c_int], C.c_char_p),
         "mop_plan_info": ([vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)], C.c_int),
         "veff_grad_timed": ([vp, vp, i32, vp, vp, i32, C.c_double, vp, C.POINTER(C.c_float)], C.c_int),
+        "pmd_step": ([vp, vp, vp, vp, i32, C.POINTER(_PmdParams), C.c_uint64, i32, vp, vp],
+                     C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -292,6 +299,24 @@ def veff_grad(plan, R, mode=0, fd_h=1e-4, G=None, veff=None):
     _check(lib().veff_grad(plan.h, _ptr(R), R.shape[0], _ptr(G), _ptr(veff), int(mode),
                            float(fd_h), _ptr(plan.ws)), "veff_grad")
     return G, veff
+
+
+def pmd_step(plan, R, V, G, tau, nsteps=1, gamma=0.0, kT=0.0, seed=0, step0=0,
+             energies=None):
+    """nsteps B A O A B steps of the path (R, V) in place; G must hold grad V_eff(R) on
+    entry and holds that of the final R on exit.  Returns energies (nsteps, 2) float64
+    {V_eff, kinetic} after each step (a CUDA tensor)."""
+    torch = _torch()
+    for t in (R, V, G):
+        _dev_tensor(t, torch.float64)
+    if not (V.shape == R.shape and G.shape == R.shape):
+        raise ValueError("R, V and G must have the same shape")
+    if energies is None:
+        energies = torch.empty((int(nsteps), 2), dtype=torch.float64, device=R.device)
+    prm = _PmdParams(float(tau), float(gamma), float(kT), int(seed) & (2 ** 64 - 1))
+    _check(lib().pmd_step(plan.h, _ptr(R), _ptr(V), _ptr(G), R.shape[0], C.byref(prm),
+                          int(step0), int(nsteps), _ptr(energies), _ptr(plan.ws)), "pmd_step")
+    return energies
 
 
 def veff_grad_timed(plan, R, mode=0, fd_h=1e-4, G=None, veff=None):

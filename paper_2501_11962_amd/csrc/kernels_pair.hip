@@ -31,9 +31,11 @@
 //      it saves.
 //
 // Pair terms, d = x_j - x_i, r = |d|, shifted-force LJ + reaction field:
-//   g = phi_sf'(r)/r = (a12 r^-6 + a6) r^-8 + qq (2 k_rf - r^-3) + C1 r^-1,
+//   g = phi_sf'(r)/r = G6 r^-8 + qq (2 k_rf - r^-3) + C1 r^-1,   G6 = a12 r^-6 + a6,
 //       C1 = -phi'(r_c) = csf + qq crf1
-//   h = (phi'' - phi_sf'/r)/r^2 = (b12 r^-6 + b6) r^-10 + 3 qq r^-5 - C1 r^-3
+//   h = (phi'' - phi_sf'/r)/r^2 = (b12 r^-6 + b6) r^-10 + 3 qq r^-5 - C1 r^-3,
+//       where b12 r^-6 + b6 = -8 (0.75 a12 r^-6 + G6) (b12 = -14 a12, b6 = -8 a6), so
+//       the Hessian kernel reads one table entry {a12, a6, csf, 0.75 a12} per pair
 //   F_i += g d,   (H v)_i += g (v_i - v_j) + h (d . (v_i - v_j)) d   (j: the opposite)
 #include <algorithm>
 
@@ -44,6 +46,11 @@ namespace mop {
 
 // Ring fields (one LDS array [field][entry] per wave; ints stored as float bits).
 constexpr int F_X = 0, F_Y = 1, F_Z = 2, F_Q = 3, F_K = 4, F_T = 5, F_S = 6, F_J = 7;
+
+// Table entries per type pair: force kernels keep {a12, a6, csf, e0lj} and
+// {b12, b6, c12, c6} interleaved (the second for energies); the Hessian kernel one.
+template <int MODE>
+constexpr int TAB_STRIDE = MODE == 1 ? 1 : 2;
 
 template <int MODE, int N3>
 struct Fields {
@@ -93,10 +100,12 @@ __device__ __forceinline__ void pair_term(const IAtom& I, const PairK& P, const 
     const float rinv2 = rinv * rinv;
     const float rinv6 = rinv2 * rinv2 * rinv2;
     const float rinv3 = rinv2 * rinv;
-    const float4 T = tabrow[2 * tj];
+    const float4 T = tabrow[TAB_STRIDE<MODE> * tj];
     const float qq = I.q * qj;
     const float C1 = fmaf(qq, P.crf1, T.z);
-    float g = fmaf(T.x, rinv6, T.y) * rinv6 * rinv2;
+    const float G6 = fmaf(T.x, rinv6, T.y);
+    const float rinv8 = rinv6 * rinv2;
+    float g = G6 * rinv8;
     g = fmaf(qq, P.krf2 - rinv3, g);
     g = fmaf(C1, rinv, g);
     g = in ? g : 0.0f;
@@ -123,9 +132,8 @@ __device__ __forceinline__ void pair_term(const IAtom& I, const PairK& P, const 
             en = in ? e : 0.0f;
         }
     } else {
-        const float4 T2 = tabrow[2 * tj + 1];
-        const float rinv4 = rinv2 * rinv2;
-        float h = fmaf(T2.x, rinv6, T2.y) * rinv6 * rinv4;
+        const float h6 = fmaf(T.w, rinv6, G6);
+        float h = h6 * (rinv8 * (-8.0f * rinv2));
         h = fmaf(3.0f * qq, rinv3 * rinv2, h);
         h = fmaf(-C1, rinv3, h);
         h = in ? h : 0.0f;
@@ -163,12 +171,17 @@ __global__ void __launch_bounds__(64 * PW) k_pair(const SegDev* __restrict__ seg
     const SegDev* __restrict__ sg = segs + p;
     const int nt = sg->s.nt;
     const int ntm = L.ntmax;
-    float4* s_tab = s_dyn;  // interleaved: [2k] pair constants, [2k+1] second-derivative/energy
-    float* s_ring = reinterpret_cast<float*>(s_dyn + 2 * ntm * ntm);
+    constexpr int TS = TAB_STRIDE<MODE>;
+    float4* s_tab = s_dyn;
+    float* s_ring = reinterpret_cast<float*>(s_dyn + TS * ntm * ntm);
     int* s_cl = reinterpret_cast<int*>(s_ring + PW * NF * RING);
     for (int t = threadIdx.x; t < nt * nt; t += 64 * PW) {
-        s_tab[2 * t] = sg->s.tab[t];
-        s_tab[2 * t + 1] = sg->s.tab2[t];
+        if (MODE == 1) {
+            s_tab[t] = sg->s.tabh[t];
+        } else {
+            s_tab[2 * t] = sg->s.tab[t];
+            s_tab[2 * t + 1] = sg->s.tab2[t];
+        }
     }
     __syncthreads();  // the only block barrier: waves are independent from here on
 
@@ -217,7 +230,7 @@ __global__ void __launch_bounds__(64 * PW) k_pair(const SegDev* __restrict__ seg
     I.q = __uint_as_float(ui.w);
     I.key2 = mi.x + 2;
     I.tiN = mi.y * nt;
-    const float4* tabrow = s_tab + 2 * I.tiN;
+    const float4* tabrow = s_tab + TS * I.tiN;
     I.ux = ui.x;
     I.uy = ui.y;
     I.uz = ui.z;
@@ -279,20 +292,26 @@ __global__ void __launch_bounds__(64 * PW) k_pair(const SegDev* __restrict__ seg
                        (fmaxf(-loz, hiz) + rcs >= 0.5f * sg->s.Lf[2]);
     const int cx = fixed_bin(ref.x, ncx), cy = fixed_bin(ref.y, ncy);
 
-    // z window of candidate atoms, in z bins
-    bool fullz = (hiz - loz + 2.0f * rcs) >= sg->s.Lf[2];
-    int zb0 = 0, zb1 = nzb - 1;
-    bool zwrap = false;
-    if (!fullz) {
-        const long long dlo = (long long)floorf((loz - rcs) / sz);
-        const long long dhi = (long long)ceilf((hiz + rcs) / sz);
-        const uint32_t zlo = ucz + (uint32_t)dlo;
-        const uint32_t zhi = ucz + (uint32_t)dhi;
-        zb0 = fixed_bin(zlo, nzb);
-        zb1 = fixed_bin(zhi, nzb);
-        zwrap = zlo > zhi;
-        if (zwrap && zb1 + 1 >= zb0) fullz = true;
-    }
+    // z window of candidate atoms of a column whose rectangle is (gx, gy) away from the
+    // bounding box: |z - box| < sqrt(rcs^2 - gx^2 - gy^2), in z bins (per lane)
+    const float Lz = sg->s.Lf[2];
+    auto zwindow = [&](float g2, bool& fullz, bool& zwrap, int& zb0, int& zb1) {
+        const float hz = sqrtf(fmaxf(rcs2 - g2, 0.0f));
+        fullz = (hiz - loz + 2.0f * hz) >= Lz;
+        zb0 = 0;
+        zb1 = nzb - 1;
+        zwrap = false;
+        if (!fullz) {
+            const long long dlo = (long long)floorf((loz - hz) / sz);
+            const long long dhi = (long long)ceilf((hiz + hz) / sz);
+            const uint32_t zlo = ucz + (uint32_t)dlo;
+            const uint32_t zhi = ucz + (uint32_t)dhi;
+            zb0 = fixed_bin(zlo, nzb);
+            zb1 = fixed_bin(zhi, nzb);
+            zwrap = zlo > zhi;
+            if (zwrap && zb1 + 1 >= zb0) fullz = true;
+        }
+    };
     const float bcx = 0.5f * (lox + hix), bhx = 0.5f * (hix - lox);
     const float bcy = 0.5f * (loy + hiy), bhy = 0.5f * (hiy - loy);
     const float xref = (float)ucx * sx, yref = (float)ucy * sy;
@@ -431,12 +450,13 @@ __global__ void __launch_bounds__(64 * PW) k_pair(const SegDev* __restrict__ seg
     // global-load latency of chunk q+1 overlaps the tests, ring writes and pair
     // evaluations of chunk q.
     auto process = [&](int T) {
-        const uint4 z4 = make_uint4(0u, 0u, 0u, 0u);
+        // lanes without a candidate load slot 0 (always present) and are rejected by
+        // the slot test below; no select between pointers, so the loads stay global
         int nslot = (lane >> 3) < T ? clist[lane >> 3] * CLUSTER + (lane & 7) : -1;
-        uint4 nuj = nslot >= 0 ? upos[nslot] : z4;
-        int2 nmj = nslot >= 0 ? umeta[nslot] : make_int2(DUMMY_KEY, 0);
+        uint4 nuj = upos[max(nslot, 0)];
+        int2 nmj = umeta[max(nslot, 0)];
         float4 njv = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (MODE == 1 && nslot >= 0) njv = vs[nslot];
+        if (MODE == 1) njv = vs[max(nslot, 0)];
         for (int q = 0; q < T; q += 8) {
             const int slot = nslot;
             const uint4 uj = nuj;
@@ -523,6 +543,9 @@ __global__ void __launch_bounds__(64 * PW) k_pair(const SegDev* __restrict__ seg
             const float gy = fmaxf(0.0f, fabsf(dyc) - 0.5f * cwy - bhy);
             const int col = jxc * ncy + jyc;
             if (gx * gx + gy * gy < rcs2) {
+                bool fullz, zwrap;
+                int zb0, zb1;
+                zwindow(gx * gx + gy * gy, fullz, zwrap, zb0, zb1);
                 const int base = colstart[col];
                 const int* bo = binoff + (size_t)col * (nzb + 1);
                 const int cnt = bo[nzb];
@@ -639,7 +662,7 @@ static void launch_pair_t(const SegDev* dsegs, const SegDev* hsegs, const Launch
     const int nblk = L.pf[base.nseg];
     if (nblk == 0) return;
     const int grid = ((nblk + 7) / 8) * 8;
-    const size_t lds = 2 * (size_t)L.ntmax * L.ntmax * sizeof(float4) +
+    const size_t lds = TAB_STRIDE<MODE> * (size_t)L.ntmax * L.ntmax * sizeof(float4) +
                        (size_t)PW * Fields<MODE, N3>::NF * RING * sizeof(float) +
                        (size_t)PW * CLIST * sizeof(int);
     hipLaunchKernelGGL((k_pair<MODE, PW, N3>), dim3(grid), dim3(64 * PW), lds, st, dsegs, L, ws,

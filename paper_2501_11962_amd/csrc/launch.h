@@ -31,4 +31,12 @@ void run_finalize_hvp(const SegDev* dsegs, const SegDev* hsegs, const Launch& ba
                       const CallPtrs& cp, hipStream_t st);
 void run_status_clear(int* status, hipStream_t st);
 
+// Path integrator: the parts of one B A O A B step around the gradient evaluation.
+void run_pmd_pre(const SegDev* dsegs, const SegDev* hsegs, const Launch& base, double* R, double* V,
+                 const double* G, const PmdCoef& pc, uint64_t step, hipStream_t st);
+// energies (device, or null): {V_eff, kinetic} of path p at energies + p * stride.
+void run_pmd_post(const SegDev* dsegs, const SegDev* hsegs, const Launch& base, double* V,
+                  const double* G, const PmdCoef& pc, char* ws, double* energies, int stride,
+                  hipStream_t st);
+
 }  // namespace mop

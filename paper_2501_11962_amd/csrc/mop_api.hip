@@ -318,16 +318,17 @@ int mop_system_create(mop_ctx ctx, const mop_system_desc* d, mop_system* out) {
     // per atom
     std::vector<float> qs(Q);
     std::vector<int> typ(Q);
-    std::vector<double> c(Q), K(Q);
+    std::vector<double> c(Q), K(Q), minv(Q);
     const double sq = std::sqrt(fq);
     for (int i = 0; i < Q; ++i) {
         qs[i] = (float)(d->charge[i] * sq);
         typ[i] = d->type[i];
         c[i] = d->dt / (d->mass[i] * d->nu);
         K[i] = d->mass[i] * d->nu / (2.0 * d->dt);
+        minv[i] = 1.0 / d->mass[i];
     }
     // type-pair tables (Lorentz-Berthelot), shifted-force constants at r_cut
-    std::vector<float4> tab(nt * nt), tab2(nt * nt);
+    std::vector<float4> tab(nt * nt), tab2(nt * nt), tabh(nt * nt);
     for (int a = 0; a < nt; ++a)
         for (int b = 0; b < nt; ++b) {
             const double sg = 0.5 * (d->sigma[a] + d->sigma[b]);
@@ -341,6 +342,8 @@ int mop_system_create(mop_ctx ctx, const mop_system_desc* d, mop_system* out) {
             const double e0 = -phic - rc * csf;
             tab[a * nt + b] = make_float4((float)(-12.0 * c12), (float)(6.0 * c6), (float)csf, (float)e0);
             tab2[a * nt + b] = make_float4((float)(168.0 * c12), (float)(-48.0 * c6), (float)c12, (float)c6);
+            tabh[a * nt + b] = make_float4((float)(-12.0 * c12), (float)(6.0 * c6), (float)csf,
+                                           (float)(-9.0 * c12));
         }
     // bond CSR (each bond listed for both atoms)
     std::vector<int> bstart(Q + 1, 0), bpart(2 * (size_t)d->nbonds);
@@ -371,12 +374,14 @@ int mop_system_create(mop_ctx ctx, const mop_system_desc* d, mop_system* out) {
     if (!e) e = upload(sys, typ.data(), Q, &s.type);
     if (!e) e = upload(sys, c.data(), Q, &s.c);
     if (!e) e = upload(sys, K.data(), Q, &s.K);
+    if (!e) e = upload(sys, minv.data(), Q, &s.minv);
     if (!e) e = upload(sys, bstart.data(), Q + 1, &s.bstart);
     if (!e) e = upload(sys, bpart.data(), bpart.size(), &s.bpart);
     if (!e) e = upload(sys, br0.data(), br0.size(), &s.br0);
     if (!e) e = upload(sys, bk.data(), bk.size(), &s.bk);
     if (!e) e = upload(sys, tab.data(), tab.size(), &s.tab);
     if (!e) e = upload(sys, tab2.data(), tab2.size(), &s.tab2);
+    if (!e) e = upload(sys, tabh.data(), tabh.size(), &s.tabh);
     if (e) {
         mop_system_destroy(sys);
         return e;
@@ -598,6 +603,35 @@ int veff_grad_timed(mop_plan plan, const double* R, int32_t N, double* G, double
     }
     for (int k = 0; k <= MOP_NPHASES; ++k) (void)hipEventDestroy(ev[k]);
     return rc;
+}
+
+int pmd_step(mop_plan plan, double* R, double* V, double* G, int32_t N,
+             const mop_pmd_params* prm, uint64_t step0, int32_t nsteps, double* energies,
+             void* ws) {
+    if (!plan || !R || !V || !G || !prm || !ws) return MOP_EINVAL;
+    if (N < 1 || nsteps < 1) return MOP_EINVAL;
+    if (N > plan->max_beads) return MOP_ESIZE;
+    if (!(prm->tau > 0.0) || !(prm->gamma >= 0.0) || !(prm->kT >= 0.0)) return MOP_EINVAL;
+    if (!std::isfinite(prm->tau) || !std::isfinite(prm->gamma) || !std::isfinite(prm->kT))
+        return MOP_EINVAL;
+    hipStream_t st = plan->sys->ctx->stream;
+    PmdCoef pc;
+    pc.tau = prm->tau;
+    pc.c1 = std::exp(-prm->gamma * prm->tau);
+    pc.c2 = prm->gamma > 0.0 ? std::sqrt((1.0 - pc.c1 * pc.c1) * prm->kT) : 0.0;
+    pc.seed = prm->seed;
+    CallPtrs cp = call_ptrs(ws);
+    cp.R = R;
+    cp.G = G;
+    const Launch L = one_path(N, N > 1 ? N - 1 : 1);
+    for (int32_t k = 0; k < nsteps; ++k) {
+        double* ek = energies ? energies + 2 * (size_t)k : nullptr;
+        run_pmd_pre(plan->dseg, &plan->hseg, L, R, V, G, pc, step0 + (uint64_t)k, st);
+        cp.veff = nullptr;
+        path_sequence(plan->dseg, &plan->hseg, L, cp, true, 0, plan->waves, plan->newton3, st);
+        run_pmd_post(plan->dseg, &plan->hseg, L, V, G, pc, cp.ws, ek, 2, st);
+    }
+    return finish(plan->sys->ctx);
 }
 
 int mop_batch_create(int32_t P, const mop_plan* plans, const int32_t* N, mop_batch* out) {

@@ -58,12 +58,15 @@ struct SysDev {
     const int* type;      // [Q]
     const double* c;      // [Q] dt / (m nu)
     const double* K;      // [Q] m nu / (2 dt)
+    const double* minv;   // [Q] 1 / m (path dynamics)
     const int* bstart;    // [Q + 1] bond CSR (each bond listed for both atoms)
     const int* bpart;     // partner atom
     const double* br0;
     const double* bk;
     const float4* tab;    // [nt*nt] {a12 = -12 c12, a6 = 6 c6, csf = -phi_LJ'(rc), e0lj}
     const float4* tab2;   // [nt*nt] {b12 = 168 c12, b6 = -48 c6, c12, c6}
+    const float4* tabh;   // [nt*nt] {a12, a6, csf, 0.75 a12}: the Hessian kernel's table
+                          // (b12 = -14 a12 and b6 = -8 a6 follow from a12, a6)
 };
 
 // One path (segment) of a launch.  Byte offsets are relative to the workspace base.
@@ -86,6 +89,14 @@ struct Launch {
     int pf[MAXSEG + 1];   // block prefix per segment
     int N[MAXSEG];        // beads of each path in this call
     int nb[MAXSEG];       // pair beads of each path in this call
+};
+
+// Coefficients of one step of the path integrator.
+struct PmdCoef {
+    double tau;           // time step (ps)
+    double c1;            // exp(-gamma tau)
+    double c2;            // sqrt((1 - c1^2) kT); 0 without thermostat
+    uint64_t seed;        // key of the normal deviates
 };
 
 // Pointers of one call (device).
