@@ -106,6 +106,13 @@ typedef struct {
  *               gather the partner's share with atomic adds; summation order then
  *               depends on scheduling.  Default: every pair from both sides without
  *               atomics, which is the faster variant on MI355X.
+ *   list_cap    neighbour-list entries per 8-atom cluster.  veff_grad (exact mode)
+ *               records, in its force pass, which atoms passed each cluster's
+ *               neighbour search, and its Hessian pass reads them back instead of
+ *               searching again; a cluster with more survivors than list_cap is
+ *               searched again.  0: sized from the mean density (about 1.6 times the
+ *               expected count); negative: no lists.  The workspace grows by
+ *               4 * list_cap bytes per cluster and pair bead.
  */
 #define MOP_PLAN_NEWTON3 1
 typedef struct {
@@ -113,6 +120,7 @@ typedef struct {
     double zbin;
     int32_t waves;
     int32_t flags;
+    int32_t list_cap;
 } mop_plan_opts;
 
 /* Host-only validation of a system description (no device needed).  Returns MOP_OK,

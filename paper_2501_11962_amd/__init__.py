@@ -55,7 +55,7 @@ class _PmdParams(C.Structure):
 
 class _Opts(C.Structure):
     _fields_ = [("col_width", C.c_double), ("zbin", C.c_double), ("waves", C.c_int32),
-                ("flags", C.c_int32)]
+                ("flags", C.c_int32), ("list_cap", C.c_int32)]
 
 
 EXPORTS = [
@@ -218,12 +218,13 @@ class System:
 class Plan:
     """Plan for up to max_beads beads; owns a device workspace (torch uint8)."""
 
-    def __init__(self, system, max_beads, col_width=0.0, zbin=0.0, waves=0, newton3=False):
+    def __init__(self, system, max_beads, col_width=0.0, zbin=0.0, waves=0, newton3=False,
+                 list_cap=0):
         torch = _torch()
         self.system = system
         self.Q = system.Q
         self.max_beads = int(max_beads)
-        o = _Opts(col_width, zbin, waves, MOP_PLAN_NEWTON3 if newton3 else 0)
+        o = _Opts(col_width, zbin, waves, MOP_PLAN_NEWTON3 if newton3 else 0, int(list_cap))
         h = C.c_void_p()
         _check(lib().mop_plan_create(system.h, self.max_beads, C.byref(o), C.byref(h)),
                "mop_plan_create")

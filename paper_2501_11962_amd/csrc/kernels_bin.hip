@@ -4,6 +4,8 @@
 // (column, z bin), scan bins inside each column, scan padded column counts, scatter
 // atoms into slot order, and fill each column's padding slots.  The counting sort
 // replaces the pair search of the physical force routine (do_force, section 2.1).
+// Inside a bin atoms are ordered by index (the histogram's atomic ranks only reserve
+// places), so the slot order, and with it every pair sum, is the same on every call.
 // HBM-bound, O(Q) per bead.
 #include "device_common.h"
 #include "launch.h"
@@ -113,7 +115,17 @@ __global__ void __launch_bounds__(CSB) k_bin_colstart(const SegDev* __restrict__
     if (threadIdx.x == CSB - 1) cs[ncol] = sh[CSB - 1];
 }
 
-// Scatter atoms into slot order.
+// Atom i's bin: first slot and atom count.
+__device__ __forceinline__ void bin_range(const SegDev& sg, char* ws, int b, int key, int& first,
+                                          int& count) {
+    const int ncol = sg.s.ncol, nzb = sg.s.nzb;
+    const int col = key / nzb, zb = key - col * nzb;
+    const int* bo = wsp<const int>(ws, sg.o_binoff) + ((size_t)b * ncol + col) * (nzb + 1);
+    first = wsp<const int>(ws, sg.o_colstart)[(size_t)b * (ncol + 1) + col] + bo[zb];
+    count = bo[zb + 1] - bo[zb];
+}
+
+// Reserve places: the atoms of each bin in the order of their atomic ranks.
 __global__ void __launch_bounds__(EWB) k_bin_scatter(const SegDev* __restrict__ segs, Launch L, char* ws) {
     const int blk = blockIdx.x;
     const int p = find_seg(L, blk);
@@ -121,14 +133,32 @@ __global__ void __launch_bounds__(EWB) k_bin_scatter(const SegDev* __restrict__ 
     const int local = blk - L.pf[p];
     const int b = local / sg.bpb;
     const int i = (local - b * sg.bpb) * EWB + threadIdx.x;
-    const int Q = sg.s.Q, ncol = sg.s.ncol, nzb = sg.s.nzb, S = sg.s.S;
+    const int Q = sg.s.Q;
+    if (i >= Q) return;
+    const int key = (int)wsp<const uint4>(ws, sg.o_atomu)[(size_t)b * Q + i].w;
+    int first, count;
+    bin_range(sg, ws, b, key, first, count);
+    wsp<int>(ws, sg.o_tmpo)[(size_t)b * sg.s.S + first + wsp<const int>(ws, sg.o_rank)[(size_t)b * Q + i]] = i;
+}
+
+// Place each atom at its bin's first slot plus the number of atoms of the bin with a
+// smaller index.
+__global__ void __launch_bounds__(EWB) k_bin_place(const SegDev* __restrict__ segs, Launch L, char* ws) {
+    const int blk = blockIdx.x;
+    const int p = find_seg(L, blk);
+    const SegDev& sg = segs[p];
+    const int local = blk - L.pf[p];
+    const int b = local / sg.bpb;
+    const int i = (local - b * sg.bpb) * EWB + threadIdx.x;
+    const int Q = sg.s.Q, S = sg.s.S;
     if (i >= Q) return;
     const uint4 u = wsp<const uint4>(ws, sg.o_atomu)[(size_t)b * Q + i];
-    const int key = (int)u.w;
-    const int col = key / nzb, zb = key - col * nzb;
-    const int slot = wsp<const int>(ws, sg.o_colstart)[(size_t)b * (ncol + 1) + col] +
-                     wsp<const int>(ws, sg.o_binoff)[((size_t)b * ncol + col) * (nzb + 1) + zb] +
-                     wsp<const int>(ws, sg.o_rank)[(size_t)b * Q + i];
+    int first, count;
+    bin_range(sg, ws, b, (int)u.w, first, count);
+    const int* tmpo = wsp<const int>(ws, sg.o_tmpo) + (size_t)b * S + first;
+    int r = 0;
+    for (int k = 0; k < count; ++k) r += tmpo[k] < i;
+    const int slot = first + r;
     wsp<uint4>(ws, sg.o_upos)[(size_t)b * S + slot] =
         make_uint4(u.x, u.y, u.z, __float_as_uint(sg.s.qs[i]));
     wsp<int2>(ws, sg.o_umeta)[(size_t)b * S + slot] = make_int2(sg.s.key[i], sg.s.type[i]);
@@ -189,6 +219,7 @@ void run_binning(const SegDev* dsegs, const SegDev* hsegs, const Launch& base, c
     for (int p = 0; p < base.nseg; ++p) Lb.pf[p + 1] = Lb.pf[p] + base.nb[p];
     hipLaunchKernelGGL(k_bin_colstart, dim3(Lb.pf[base.nseg]), dim3(CSB), 0, st, dsegs, Lb, ws);
     hipLaunchKernelGGL(k_bin_scatter, dim3(La.pf[base.nseg]), dim3(EWB), 0, st, dsegs, La, ws);
+    hipLaunchKernelGGL(k_bin_place, dim3(La.pf[base.nseg]), dim3(EWB), 0, st, dsegs, La, ws);
     hipLaunchKernelGGL(k_bin_pad, dim3(Lc.pf[base.nseg]), dim3(EWB), 0, st, dsegs, Lc, ws);
 }
 

@@ -157,7 +157,8 @@ __device__ __forceinline__ void pair_term(const IAtom& I, const PairK& P, const 
 
 template <int MODE, int PW, int N3>
 __global__ void __launch_bounds__(64 * PW) k_pair(const SegDev* __restrict__ segs, Launch L,
-                                                 char* __restrict__ ws, int outsel, int energy_bead) {
+                                                 char* __restrict__ ws, int outsel, int energy_bead,
+                                                 int lists) {
     using FL = Fields<MODE, N3>;
     constexpr int NF = FL::NF, FV = FL::V;
     extern __shared__ float4 s_dyn[];
@@ -243,7 +244,7 @@ __global__ void __launch_bounds__(64 * PW) k_pair(const SegDev* __restrict__ seg
     }
     // bounding box relative to the reference atom, then to its own centre
     float lox, hix, loy, hiy, loz, hiz;
-    auto bbox = [&](float x, float y, float z) {
+    auto bbox = [&](float x, float y, float z) __attribute__((always_inline)) {
         lox = I.v ? x : 3.0e38f;
         hix = I.v ? x : -3.0e38f;
         loy = I.v ? y : 3.0e38f;
@@ -295,7 +296,8 @@ __global__ void __launch_bounds__(64 * PW) k_pair(const SegDev* __restrict__ seg
     // z window of candidate atoms of a column whose rectangle is (gx, gy) away from the
     // bounding box: |z - box| < sqrt(rcs^2 - gx^2 - gy^2), in z bins (per lane)
     const float Lz = sg->s.Lf[2];
-    auto zwindow = [&](float g2, bool& fullz, bool& zwrap, int& zb0, int& zb1) {
+    auto zwindow = [&](float g2, bool& fullz, bool& zwrap, int& zb0, int& zb1)
+                       __attribute__((always_inline)) {
         const float hz = sqrtf(fmaxf(rcs2 - g2, 0.0f));
         fullz = (hiz - loz + 2.0f * hz) >= Lz;
         zb0 = 0;
@@ -325,6 +327,18 @@ __global__ void __launch_bounds__(64 * PW) k_pair(const SegDev* __restrict__ seg
 
     float* ring = s_ring + wave * NF * RING;
     int* clist = s_cl + wave * CLIST;
+
+    // neighbour lists (full-shell kernels): the force pass records the slots that pass
+    // the search, the Hessian pass of the same bead replays them
+    const int lcap = sg->s.lcap;
+    const bool rec = !N3 && MODE == 0 && lists == 1 && lcap > 0;
+    const bool rpl = !N3 && MODE == 1 && lists == 2 && lcap > 0;
+    int* __restrict__ nl = nullptr;
+    int* __restrict__ nlc = nullptr;
+    if (rec || rpl) {
+        nl = wsp<int>(ws, sg->o_nl) + ((size_t)b * cpb + c) * lcap;
+        nlc = wsp<int>(ws, sg->o_nlc) + (size_t)b * cpb + c;
+    }
 
     // ---- own cluster (N3): one 8 x 8 block, both sides, weight 1/2 for energies ----
     if (N3) {
@@ -371,7 +385,8 @@ __global__ void __launch_bounds__(64 * PW) k_pair(const SegDev* __restrict__ seg
     // ---- 8 j-atoms x 8 i-atoms per step from ring entries [base, base + count) ------
     // base is a multiple of 64, so reads of a chunk never wrap and every field of every
     // step is one immediate offset from the same address.
-    auto eval_t = [&]<bool EX, bool WE, bool FULL>(int base, int count) {
+    auto eval_t = [&]<bool EX, bool WE, bool FULL>(int base, int count)
+                      __attribute__((always_inline)) {
         float* rb = ring + (base & (RING - 1)) + jslot;
         const int nsteps = FULL ? 8 : (count + 7) >> 3;
 #pragma unroll
@@ -435,7 +450,7 @@ __global__ void __launch_bounds__(64 * PW) k_pair(const SegDev* __restrict__ seg
             }
         }
     };
-    auto eval = [&]<bool FULL>(int base, int count) {
+    auto eval = [&]<bool FULL>(int base, int count) __attribute__((always_inline)) {
         if (exact) {
             if (wantE) eval_t.template operator()<true, true, FULL>(base, count);
             else eval_t.template operator()<true, false, FULL>(base, count);
@@ -449,7 +464,7 @@ __global__ void __launch_bounds__(64 * PW) k_pair(const SegDev* __restrict__ seg
     // Candidate atoms are loaded one chunk (8 clusters) ahead of their use, so the
     // global-load latency of chunk q+1 overlaps the tests, ring writes and pair
     // evaluations of chunk q.
-    auto process = [&](int T) {
+    auto process = [&](int T) __attribute__((always_inline)) {
         // lanes without a candidate load slot 0 (always present) and are rejected by
         // the slot test below; no select between pointers, so the loads stay global
         int nslot = (lane >> 3) < T ? clist[lane >> 3] * CLUSTER + (lane & 7) : -1;
@@ -491,6 +506,7 @@ __global__ void __launch_bounds__(64 * PW) k_pair(const SegDev* __restrict__ seg
                                                       __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
             wave_sync();  // previous reads of the ring are done before it is overwritten
             if (pass) {
+                if (rec && wp + off < lcap) nl[wp + off] = slot;
                 float* re = ring + ((wp + off) & (RING - 1));
                 re[F_X * RING] = jx;
                 re[F_Y * RING] = jy;
@@ -520,8 +536,62 @@ __global__ void __launch_bounds__(64 * PW) k_pair(const SegDev* __restrict__ seg
         }
     };
 
+    // ---- replay of a recorded list: 64 entries per chunk, loads two chunks ahead ----
+    auto replay = [&](int cnt) __attribute__((always_inline)) {
+        int s1 = lane < cnt ? nl[lane] : -1;
+        int s2 = 64 + lane < cnt ? nl[64 + lane] : -1;
+        uint4 nuj = upos[max(s1, 0)];
+        int2 nmj = umeta[max(s1, 0)];
+        float4 njv = vs[max(s1, 0)];
+        for (int k0 = 0; k0 < cnt; k0 += 64) {
+            const uint4 uj = nuj;
+            const int2 mj = nmj;
+            const float4 jv = njv;
+            const int n = min(64, cnt - k0);
+            s1 = s2;
+            nuj = upos[max(s1, 0)];
+            nmj = umeta[max(s1, 0)];
+            njv = vs[max(s1, 0)];
+            s2 = k0 + 128 + lane < cnt ? nl[k0 + 128 + lane] : -1;
+            float jx, jy, jz;
+            if (exact) {
+                jx = __uint_as_float(uj.x);
+                jy = __uint_as_float(uj.y);
+                jz = __uint_as_float(uj.z);
+            } else {
+                jx = (float)(int)(uj.x - ucx) * sx;
+                jy = (float)(int)(uj.y - ucy) * sy;
+                jz = (float)(int)(uj.z - ucz) * sz;
+            }
+            wave_sync();  // the previous chunk's reads of the ring are done
+            if (lane < n) {
+                float* re = ring + lane;
+                re[F_X * RING] = jx;
+                re[F_Y * RING] = jy;
+                re[F_Z * RING] = jz;
+                re[F_Q * RING] = __uint_as_float(uj.w);
+                re[F_K * RING] = __int_as_float(mj.x);
+                re[F_T * RING] = __int_as_float(mj.y);
+                re[FV * RING] = jv.x;
+                re[(FV + 1) * RING] = jv.y;
+                re[(FV + 2) * RING] = jv.z;
+            }
+            wave_sync();
+            if (n == 64) eval.template operator()<true>(0, 64);
+            else eval.template operator()<false>(0, n);
+        }
+    };
+    bool searched = true;
+    if (rpl) {
+        const int cnt = *nlc;
+        if (cnt <= lcap) {
+            replay(cnt);
+            searched = false;
+        }
+    }
+
     // ---- column stencil, 64 columns per pass ---------------------------------------
-    const int wx = sg->s.wx, wy = sg->s.wy, nst = wx * wy;
+    const int wx = sg->s.wx, wy = sg->s.wy, nst = searched ? wx * wy : 0;
     for (int k0 = 0; k0 < nst; k0 += 64) {
         const int k = k0 + lane;
         int a0 = 0, a1 = 0, b0 = 0, b1 = 0;
@@ -596,6 +666,7 @@ __global__ void __launch_bounds__(64 * PW) k_pair(const SegDev* __restrict__ seg
     }
     // ---- remaining ring entries ---------------------------------------------------
     if (wp - rp > 0) eval.template operator()<false>(rp, wp - rp);
+    if (rec && lane == 0) *nlc = wp;
 
     // ---- reduce over the 8 j lanes of each i atom and store ------------------------
 #pragma unroll
@@ -651,7 +722,7 @@ __global__ void __launch_bounds__(EWB) k_unsort(const SegDev* __restrict__ segs,
 
 template <int MODE, int PW, int N3>
 static void launch_pair_t(const SegDev* dsegs, const SegDev* hsegs, const Launch& base, char* ws,
-                          int outsel, int energy_bead, hipStream_t st) {
+                          int outsel, int energy_bead, int lists, hipStream_t st) {
     Launch L = base;
     L.pf[0] = 0;
     L.ntmax = 1;
@@ -666,34 +737,34 @@ static void launch_pair_t(const SegDev* dsegs, const SegDev* hsegs, const Launch
                        (size_t)PW * Fields<MODE, N3>::NF * RING * sizeof(float) +
                        (size_t)PW * CLIST * sizeof(int);
     hipLaunchKernelGGL((k_pair<MODE, PW, N3>), dim3(grid), dim3(64 * PW), lds, st, dsegs, L, ws,
-                       outsel, energy_bead);
+                       outsel, energy_bead, lists);
 }
 
 template <int MODE, int N3>
 static void launch_pair_w(const SegDev* dsegs, const SegDev* hsegs, const Launch& base, char* ws,
-                          int outsel, int energy_bead, int waves, hipStream_t st) {
+                          int outsel, int energy_bead, int waves, int lists, hipStream_t st) {
     switch (waves) {
-        case 1: launch_pair_t<MODE, 1, N3>(dsegs, hsegs, base, ws, outsel, energy_bead, st); break;
-        case 2: launch_pair_t<MODE, 2, N3>(dsegs, hsegs, base, ws, outsel, energy_bead, st); break;
-        case 8: launch_pair_t<MODE, 8, N3>(dsegs, hsegs, base, ws, outsel, energy_bead, st); break;
-        default: launch_pair_t<MODE, 4, N3>(dsegs, hsegs, base, ws, outsel, energy_bead, st); break;
+        case 1: launch_pair_t<MODE, 1, N3>(dsegs, hsegs, base, ws, outsel, energy_bead, lists, st); break;
+        case 2: launch_pair_t<MODE, 2, N3>(dsegs, hsegs, base, ws, outsel, energy_bead, lists, st); break;
+        case 8: launch_pair_t<MODE, 8, N3>(dsegs, hsegs, base, ws, outsel, energy_bead, lists, st); break;
+        default: launch_pair_t<MODE, 4, N3>(dsegs, hsegs, base, ws, outsel, energy_bead, lists, st); break;
     }
 }
 
 void run_pair(const SegDev* dsegs, const SegDev* hsegs, const Launch& base, char* ws, int mode,
-              int outsel, int energy_bead, int waves, int newton3, hipStream_t st) {
+              int outsel, int energy_bead, int waves, int newton3, hipStream_t st, int lists) {
     if (mode == 1) outsel = 1;
     if (newton3) {
-        if (mode == 0) launch_pair_w<0, 1>(dsegs, hsegs, base, ws, outsel, energy_bead, waves, st);
-        else launch_pair_w<1, 1>(dsegs, hsegs, base, ws, outsel, energy_bead, waves, st);
+        if (mode == 0) launch_pair_w<0, 1>(dsegs, hsegs, base, ws, outsel, energy_bead, waves, 0, st);
+        else launch_pair_w<1, 1>(dsegs, hsegs, base, ws, outsel, energy_bead, waves, 0, st);
         Launch L = base;
         L.pf[0] = 0;
         for (int p = 0; p < base.nseg; ++p) L.pf[p + 1] = L.pf[p] + base.nb[p] * hsegs[p].bpb;
         if (L.pf[base.nseg] > 0)
             hipLaunchKernelGGL(k_unsort, dim3(L.pf[base.nseg]), dim3(EWB), 0, st, dsegs, L, ws, outsel);
     } else {
-        if (mode == 0) launch_pair_w<0, 0>(dsegs, hsegs, base, ws, outsel, energy_bead, waves, st);
-        else launch_pair_w<1, 0>(dsegs, hsegs, base, ws, outsel, energy_bead, waves, st);
+        if (mode == 0) launch_pair_w<0, 0>(dsegs, hsegs, base, ws, outsel, energy_bead, waves, lists, st);
+        else launch_pair_w<1, 0>(dsegs, hsegs, base, ws, outsel, energy_bead, waves, lists, st);
     }
 }
 

@@ -178,6 +178,7 @@ static size_t layout(SegDev& sg, int maxb, int maxN, size_t base) {
     take(sg.o_slotof, B * Q * 4);
     take(sg.o_atomu, B * Q * 16);
     take(sg.o_rank, B * Q * 4);
+    take(sg.o_tmpo, B * S * 4);
     take(sg.o_bincnt, B * nc * nz * 4);
     take(sg.o_binoff, B * nc * (nz + 1) * 4);
     take(sg.o_colcnt, B * nc * 4);
@@ -192,6 +193,11 @@ static size_t layout(SegDev& sg, int maxb, int maxN, size_t base) {
     take(sg.o_rpart, (size_t)std::max(maxN, maxb) * sg.bpb * 16);
     take(sg.o_dmax, (size_t)std::max(maxN, 1) * 8);
     take(sg.o_eres, 4 * 8);
+    sg.o_nl = sg.o_nlc = 0;
+    if (s.lcap > 0) {
+        take(sg.o_nl, B * s.cpb * (size_t)s.lcap * 4);
+        take(sg.o_nlc, B * s.cpb * 4);
+    }
     sg.maxb = maxb;
     sg.maxN = maxN;
     return o;
@@ -227,6 +233,23 @@ static SysDev plan_geometry(const mop_system_s* sys, const mop_plan_opts* opts) 
     s.cw[1] = (float)cwy;
     s.rcs = (float)rcs;
     s.rcs2 = (float)(rcs * rcs);
+    // neighbour-list capacity: 1.6 x the expected number of atoms within the search
+    // radius of an 8-atom cluster's box (cw x cw x the height 8 atoms fill at the mean
+    // density), rounded up to a multiple of 64
+    const int lc = opts ? opts->list_cap : 0;
+    if (lc > 0) {
+        s.lcap = lc;
+    } else if (lc < 0) {
+        s.lcap = 0;
+    } else {
+        const double rho = s.Q / (L[0] * L[1] * L[2]);
+        const double a = cwx, b = cwy, c = std::min(L[2], CLUSTER / (rho * a * b)), r = rcs;
+        const double pi = 3.14159265358979323846;
+        const double vol = a * b * c + 2.0 * (a * b + b * c + c * a) * r +
+                           pi * r * r * (a + b + c) + 4.0 / 3.0 * pi * r * r * r;
+        const double est = std::min(1.6 * rho * vol, (double)s.S);
+        s.lcap = std::max(64, ((int)std::ceil(est) + 63) & ~63);
+    }
     return s;
 }
 
@@ -515,7 +538,9 @@ static void path_sequence(const SegDev* dsegs, const SegDev* hsegs, const Launch
     // forces of beads 1..N-1 (bead 1 alone for N = 1), energy of bead 1
     run_binning(dsegs, hsegs, base, cp.ws, cp.R, 0, 0.0, st);
     mark(1);
-    run_pair(dsegs, hsegs, base, cp.ws, 0, 0, 0, waves, n3, st);
+    // exact gradients: the force pass records neighbour lists for the Hessian pass
+    const int lists = (grad && mode == 0) ? 1 : 0;
+    run_pair(dsegs, hsegs, base, cp.ws, 0, 0, 0, waves, n3, st, lists);
     mark(2);
     run_resid(dsegs, hsegs, base, cp, st);
     mark(3);
@@ -526,7 +551,7 @@ static void path_sequence(const SegDev* dsegs, const SegDev* hsegs, const Launch
             Lh.nb[p] = base.N[p] - 1;
             any = any || Lh.nb[p] > 0;
         }
-        if (any && mode == 0) run_pair(dsegs, hsegs, Lh, cp.ws, 1, 0, -1, waves, n3, st);
+        if (any && mode == 0) run_pair(dsegs, hsegs, Lh, cp.ws, 1, 0, -1, waves, n3, st, 2 * lists);
         mark(4);
         if (any && mode == 1) {
             run_binning(dsegs, hsegs, Lh, cp.ws, cp.R, +1, cp.fd_h, st);

@@ -11,6 +11,9 @@
 //     vs    float4 the vector of a Hessian-vector product, slot order
 //     fs    float  x3 pair sums in slot order (structure of arrays), Newton-3 kernels
 //   Per atom (original order): slotof, pair force / pair HVP outputs (float4).
+//   Per cluster: the neighbour list a force pass records for the Hessian pass of the
+//     same bead (nl: int [lcap] slots of the atoms that passed the search, in search
+//     order; nlc: their count, which may exceed lcap, then the list is incomplete).
 // Per path: FP64 residuals d^n [(N-1)][Q][3], reduction partials, per-bead max |d|^2.
 #pragma once
 
@@ -38,6 +41,7 @@ struct SysDev {
     int Q, ncx, ncy, ncol, nzb, nt;
     int S;            // slots per bead (multiple of 8)
     int cpb;          // clusters per bead (S / 8)
+    int lcap;         // neighbour-list entries per cluster (0: no lists)
     int allx, ally;   // 1: the column stencil spans every column along that axis
     int rx, ry;       // stencil half widths (columns) when not spanning
     int wx, wy;       // stencil widths (columns)
@@ -79,7 +83,7 @@ struct SegDev {
     int bpb;              // elementwise blocks per bead: ceil(Q / EWB)
     size_t o_upos, o_umeta, o_orig, o_slotof, o_atomu, o_rank, o_bincnt, o_binoff,
         o_colcnt, o_colstart, o_vs, o_fs, o_f32, o_f32m, o_hv32, o_epart, o_d64, o_rpart,
-        o_dmax, o_eres;
+        o_dmax, o_eres, o_nl, o_nlc, o_tmpo;
 };
 
 // Per-launch description, passed by value.

@@ -318,6 +318,8 @@ def test_graph_replay_matches_eager(mop, ctx):
     ctx.set_stream()
     torch.cuda.synchronize()
     Go, vo = OP.veff_grad(Model(s), R)
+    Ge, ve = mop.veff_grad(plan, Rt)  # eager reference for bit-level comparison
+    Ge, ve = Ge.cpu().numpy(), float(ve[0])
     for k in range(4):
         # eager work on the same workspace between replays (different input)
         Rk = Rt + 1e-3 * (k + 1)
@@ -330,7 +332,29 @@ def test_graph_replay_matches_eager(mop, ctx):
         say(f"[graph] replay {k}: G relL2 {e:.2e}, V_eff rel {abs(float(v[0]) - vo) / abs(vo):.2e}")
         assert e < TOL_G
         assert abs(float(v[0]) - vo) < TOL_V * abs(vo)
+        # binning orders atoms deterministically: replays equal the eager call exactly
+        assert np.array_equal(G.cpu().numpy(), Ge) and float(v[0]) == ve
     assert plan.status() == 0
+
+
+def test_repeated_calls_bit_identical(mop, ctx):
+    """Every call orders the atoms of a bin by index, so the pair sums, and the gradient,
+    do not depend on scheduling: repeated calls give identical bits (also for
+    bead_forces and bead_hvp)."""
+    s = W.water_box(1002, seed=9, rc=1.0)
+    N = 4
+    R, _, _ = W.random_walk_path(s, N, 29)
+    plan = mop.Plan(mop.System(ctx, s), N)
+    Rt = cuda(R)
+    G0, v0 = (x.cpu().numpy() for x in mop.veff_grad(plan, Rt))
+    F0 = mop.bead_forces(plan, Rt)[0].cpu().numpy()
+    Vt = cuda(np.random.default_rng(3).normal(0.0, 1e-3, R.shape))
+    H0 = mop.bead_hvp(plan, Rt, Vt).cpu().numpy()
+    for _ in range(3):
+        G1, v1 = (x.cpu().numpy() for x in mop.veff_grad(plan, Rt))
+        assert np.array_equal(G0, G1) and np.array_equal(v0, v1)
+        assert np.array_equal(F0, mop.bead_forces(plan, Rt)[0].cpu().numpy())
+        assert np.array_equal(H0, mop.bead_hvp(plan, Rt, Vt).cpu().numpy())
 
 
 @pytest.mark.parametrize("name,N", [("cfg2", 5), ("water300", 5)])
@@ -383,3 +407,26 @@ def test_cfg4_full_size_sampled(mop, ctx, cl_oracle):
     ef = rel(Fg.cpu().numpy()[0], F[0])
     say(f"[cfg4] bead_forces relL2 {ef:.2e}")
     assert ef < TOL_F
+
+
+@pytest.mark.parametrize("name", ["water1002_cw03", "cfg2"])
+def test_neighbour_list_replay_is_exact(name, mop, ctx):
+    """The Hessian pass replaying the force pass's neighbour lists gives bit-identical
+    gradients to searching again (lists off), also when most clusters overflow a small
+    list and fall back to the search."""
+    s = SMALL[name]()
+    N = 5
+    R, _, _ = W.random_walk_path(s, N, 19)
+    Rt = cuda(R)
+    sysm = mop.System(ctx, s)
+    out = {}
+    for cap in (0, -1, 64):
+        plan = mop.Plan(sysm, N, list_cap=cap)
+        G, v = mop.veff_grad(plan, Rt)
+        assert plan.status() == 0
+        out[cap] = (G.cpu().numpy(), float(v[0]))
+    say(f"[lists] {name}: max |dG| auto vs off {np.max(np.abs(out[0][0] - out[-1][0])):.1e}, "
+        f"cap 64 vs off {np.max(np.abs(out[64][0] - out[-1][0])):.1e}")
+    assert np.array_equal(out[0][0], out[-1][0])
+    assert np.array_equal(out[64][0], out[-1][0])
+    assert out[0][1] == out[-1][1] == out[64][1]
