@@ -149,8 +149,8 @@ def test_langevin_free_particles_variance():
     V = V0
     G = np.zeros_like(R0)
     for n in range(1, 5):
-        R, V, G, _, ke = pmd.baoab_step(model, R, V, G, s["mass"], tau, gamma, kT, seed=17,
-                                        step=n)
+        R, V, G, _, ke, _, _ = pmd.baoab_step(model, R, V, G, s["mass"], tau, gamma, kT,
+                                              seed=17, step=n)
         mv2 = s["mass"][:, None] * V[0] ** 2
         expect = kT * (1.0 - c1 ** (2 * n))
         dof = mv2.size
