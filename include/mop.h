@@ -62,6 +62,7 @@ typedef struct mop_ctx_s* mop_ctx;
 typedef struct mop_system_s* mop_system;
 typedef struct mop_plan_s* mop_plan;
 typedef struct mop_batch_s* mop_batch;
+typedef struct mop_bias_s* mop_bias;
 
 /*
  * System description.  All pointers are HOST pointers; the arrays are copied by
@@ -180,11 +181,58 @@ int veff_grad(mop_plan plan, const double* R, int32_t N, double* G, double* veff
               int32_t mode, double fd_h, void* ws);
 
 /*
+ * Metadynamics of paths (section 1.2).  The collective variable is the end-to-end
+ * distance of eq. (8), S = s(R^N) - s(R^1), with s(R) the distance between the centres
+ * of mass of two atom groups A and B (section 3 takes the ligand and its binding pocket).
+ * Each group's centre of mass uses the minimum-image offsets of its atoms to the group's
+ * first atom, so a group must span less than half the box.  The bias is a sum of
+ * Gaussians on S,
+ *     V_bias(S) = sum_k w_k exp(-(S - S_k)^2 / (2 sigma^2)),
+ * with w_k = height (standard metadynamics) or, for bias_factor > 1 (well-tempered),
+ * height * exp(-V_bias(S_k) / (kT (bias_factor - 1))).  Its gradient acts on beads 1
+ * and N only.
+ *   groupA[nA], groupB[nB]  HOST arrays of atom indices (copied); in range, no atom twice
+ *   sigma > 0 (nm), height >= 0 (kJ/mol), bias_factor 0 or > 1 (then kT > 0), stride >= 1
+ *   (a Gaussian is deposited at steps that are multiples of stride), max_gaussians >= 1
+ *   (further deposits are dropped and set MOP_DEV_CAPACITY).
+ * mop_bias_create allocates the groups and the Gaussian history on the device (zero
+ * Gaussians); MOP_EINVAL on bad arguments.
+ */
+typedef struct {
+    int32_t nA, nB;
+    const int32_t* groupA;
+    const int32_t* groupB;
+    double sigma;
+    double height;
+    double bias_factor;
+    double kT;
+    int32_t stride;
+    int32_t max_gaussians;
+} mop_bias_desc;
+int mop_bias_create(mop_plan plan, const mop_bias_desc* desc, mop_bias* out);
+void mop_bias_destroy(mop_bias bias);
+/* Remove every deposited Gaussian (asynchronous, on the context stream). */
+int mop_bias_reset(mop_bias bias);
+/* For a path R [N][Q][3] (device): add grad V_bias to G [N][Q][3] (device, or NULL for
+ * none), write {V_bias, S} to out (two device doubles, or NULL), and, if deposit != 0,
+ * add a Gaussian at S after evaluating V_bias.  ws: the plan's workspace (status word). */
+int mop_bias_apply(mop_bias bias, const double* R, int32_t N, double* G, double* out,
+                   int32_t deposit, void* ws);
+/* Synchronise the context stream; *count = deposited Gaussians; the first
+ * min(count, capacity) centres and heights are copied to the HOST arrays (either may be
+ * NULL). */
+int mop_bias_history(mop_bias bias, int32_t* count, double* centers, double* heights,
+                     int32_t capacity);
+
+/*
  * Path molecular dynamics (eq. 4): nsteps steps of the whole polymer R [N][Q][3] under
- * F_eff = -grad V_eff, with fictitious masses read as the atoms' masses (the same for
- * every bead).  One step is the splitting B A O A B:
+ * F_eff = -grad V, V = V_eff (+ V_bias when bias is not NULL), with fictitious masses
+ * read as the atoms' masses (the same for every bead).  One step is the splitting
+ * B A O A B:
  *     V -= tau/2 G/M;  R += tau/2 V;  V = c1 V + c2 xi/sqrt(M);  R += tau/2 V;
- *     G = grad V_eff(R) (exact Hessian-vector products, as veff_grad mode 0);
+ *     G = grad V_eff(R) (exact Hessian-vector products, as veff_grad mode 0)
+ *         [+ grad V_bias(R) with the Gaussians deposited so far, then a new Gaussian at
+ *          steps step0 + k that are multiples of the bias stride];
  *     V -= tau/2 G/M
  * with c1 = exp(-gamma tau), c2 = sqrt((1 - c1^2) kT).  gamma = 0 skips the O part:
  * velocity Verlet, the constant-energy integrator of appendix A.2; gamma > 0 is the
@@ -193,10 +241,12 @@ int veff_grad(mop_plan plan, const double* R, int32_t N, double* G, double* veff
  * counter (bead * Q + atom, step0 + k, 0, 0), mapped to (0,1) as
  * (floor(x / 2^12) + 1/2) 2^-52 and through Box-Muller (outputs 0,1 -> x, y; 2,3 -> z).
  *   R, V   [N][Q][3] device doubles, updated in place (V in nm/ps)
- *   G      [N][Q][3] device doubles: on entry grad V_eff of the entry R (from
- *          veff_grad); on exit that of the final R
- *   energies  device doubles [nsteps][2] = {V_eff, kinetic energy} after each step, or
- *          NULL
+ *   G      [N][Q][3] device doubles: on entry the gradient of the total potential at the
+ *          entry R (veff_grad, then mop_bias_apply without deposit when biased); on
+ *          exit that of the final R
+ *   energies  device doubles [nsteps][4] = {V_eff, kinetic energy, V_bias, S} after each
+ *          step (the bias columns 0 without a bias), or NULL
+ *   bias   NULL, or a bias made for this plan
  *   tau > 0 (ps), gamma >= 0 (1/ps), kT >= 0 (kJ/mol); MOP_EINVAL otherwise.
  */
 typedef struct {
@@ -205,7 +255,7 @@ typedef struct {
     double kT;
     uint64_t seed;
 } mop_pmd_params;
-int pmd_step(mop_plan plan, double* R, double* V, double* G, int32_t N,
+int pmd_step(mop_plan plan, mop_bias bias, double* R, double* V, double* G, int32_t N,
              const mop_pmd_params* prm, uint64_t step0, int32_t nsteps, double* energies,
              void* ws);
 

@@ -53,6 +53,13 @@ class _PmdParams(C.Structure):
                 ("seed", C.c_uint64)]
 
 
+class _BiasDesc(C.Structure):
+    _fields_ = [("nA", C.c_int32), ("nB", C.c_int32), ("groupA", C.c_void_p),
+                ("groupB", C.c_void_p), ("sigma", C.c_double), ("height", C.c_double),
+                ("bias_factor", C.c_double), ("kT", C.c_double), ("stride", C.c_int32),
+                ("max_gaussians", C.c_int32)]
+
+
 class _Opts(C.Structure):
     _fields_ = [("col_width", C.c_double), ("zbin", C.c_double), ("waves", C.c_int32),
                 ("flags", C.c_int32), ("list_cap", C.c_int32)]
@@ -64,7 +71,8 @@ EXPORTS = [
     "mop_workspace_size", "bead_forces", "bead_hvp", "veff_energy", "veff_grad",
     "mop_batch_create", "mop_batch_destroy", "mop_batch_workspace_size",
     "mop_batch_veff_grad", "mop_status", "mop_status_clear", "mop_strerror", "mop_plan_info",
-    "veff_grad_timed", "pmd_step",
+    "veff_grad_timed", "pmd_step", "mop_bias_create", "mop_bias_destroy", "mop_bias_reset",
+    "mop_bias_apply", "mop_bias_history",
 ]
 PHASES = ["bin", "force", "resid", "hvp", "fd", "assemble"]
 
@@ -101,8 +109,13 @@ def lib():
         "mop_strerror": ([C.c_int], C.c_char_p),
         "mop_plan_info": ([vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)], C.c_int),
         "veff_grad_timed": ([vp, vp, i32, vp, vp, i32, C.c_double, vp, C.POINTER(C.c_float)], C.c_int),
-        "pmd_step": ([vp, vp, vp, vp, i32, C.POINTER(_PmdParams), C.c_uint64, i32, vp, vp],
+        "pmd_step": ([vp, vp, vp, vp, vp, i32, C.POINTER(_PmdParams), C.c_uint64, i32, vp, vp],
                      C.c_int),
+        "mop_bias_create": ([vp, C.POINTER(_BiasDesc), pp], C.c_int),
+        "mop_bias_destroy": ([vp], None),
+        "mop_bias_reset": ([vp], C.c_int),
+        "mop_bias_apply": ([vp, vp, i32, vp, vp, i32, vp], C.c_int),
+        "mop_bias_history": ([vp, C.POINTER(i32), vp, vp, i32], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -302,21 +315,69 @@ def veff_grad(plan, R, mode=0, fd_h=1e-4, G=None, veff=None):
     return G, veff
 
 
+class Bias:
+    """Metadynamics bias on the end-to-end variable of eq. (8) for paths of `plan`."""
+
+    def __init__(self, plan, groupA, groupB, sigma, height, bias_factor=0.0, kT=0.0,
+                 stride=1, max_gaussians=4096):
+        self.plan = plan
+        a = np.ascontiguousarray(groupA, np.int32)
+        b = np.ascontiguousarray(groupB, np.int32)
+        d = _BiasDesc(len(a), len(b), a.ctypes.data, b.ctypes.data, float(sigma),
+                      float(height), float(bias_factor), float(kT), int(stride),
+                      int(max_gaussians))
+        h = C.c_void_p()
+        _check(lib().mop_bias_create(plan.h, C.byref(d), C.byref(h)), "mop_bias_create")
+        self.h = h
+        self.capacity = int(max_gaussians)
+
+    def apply(self, R, G=None, deposit=False):
+        """Adds grad V_bias to G (if given); returns a CUDA tensor {V_bias, S}."""
+        torch = _torch()
+        _dev_tensor(R, torch.float64)
+        if G is not None:
+            _dev_tensor(G, torch.float64, R.shape)
+        out = torch.empty(2, dtype=torch.float64, device=R.device)
+        _check(lib().mop_bias_apply(self.h, _ptr(R), R.shape[0], _ptr(G) if G is not None else None,
+                                    _ptr(out), int(bool(deposit)), _ptr(self.plan.ws)),
+               "mop_bias_apply")
+        return out
+
+    def reset(self):
+        _check(lib().mop_bias_reset(self.h), "mop_bias_reset")
+
+    def history(self):
+        """(centres, heights) of the deposited Gaussians (numpy)."""
+        n = C.c_int32()
+        c = np.zeros(self.capacity)
+        w = np.zeros(self.capacity)
+        _check(lib().mop_bias_history(self.h, C.byref(n), c.ctypes.data, w.ctypes.data,
+                                      self.capacity), "mop_bias_history")
+        m = min(int(n.value), self.capacity)
+        return c[:m].copy(), w[:m].copy()
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.mop_bias_destroy(self.h)
+            self.h = None
+
+
 def pmd_step(plan, R, V, G, tau, nsteps=1, gamma=0.0, kT=0.0, seed=0, step0=0,
-             energies=None):
-    """nsteps B A O A B steps of the path (R, V) in place; G must hold grad V_eff(R) on
-    entry and holds that of the final R on exit.  Returns energies (nsteps, 2) float64
-    {V_eff, kinetic} after each step (a CUDA tensor)."""
+             energies=None, bias=None):
+    """nsteps B A O A B steps of the path (R, V) in place; G must hold the gradient of the
+    total potential at R on entry and holds that of the final R on exit.  Returns energies
+    (nsteps, 4) float64 {V_eff, kinetic, V_bias, S} after each step (a CUDA tensor)."""
     torch = _torch()
     for t in (R, V, G):
         _dev_tensor(t, torch.float64)
     if not (V.shape == R.shape and G.shape == R.shape):
         raise ValueError("R, V and G must have the same shape")
     if energies is None:
-        energies = torch.empty((int(nsteps), 2), dtype=torch.float64, device=R.device)
+        energies = torch.empty((int(nsteps), 4), dtype=torch.float64, device=R.device)
     prm = _PmdParams(float(tau), float(gamma), float(kT), int(seed) & (2 ** 64 - 1))
-    _check(lib().pmd_step(plan.h, _ptr(R), _ptr(V), _ptr(G), R.shape[0], C.byref(prm),
-                          int(step0), int(nsteps), _ptr(energies), _ptr(plan.ws)), "pmd_step")
+    _check(lib().pmd_step(plan.h, bias.h if bias is not None else None, _ptr(R), _ptr(V),
+                          _ptr(G), R.shape[0], C.byref(prm), int(step0), int(nsteps),
+                          _ptr(energies), _ptr(plan.ws)), "pmd_step")
     return energies
 
 

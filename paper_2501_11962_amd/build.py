@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmop.so")
-SOURCES = ["kernels_bin.hip", "kernels_pair.hip", "kernels_path.hip", "kernels_pmd.hip",
+SOURCES = ["kernels_bin.hip", "kernels_pair.hip", "kernels_path.hip", "kernels_pmd.hip", "kernels_bias.hip",
            "mop_api.hip"]
 ARCH = os.environ.get("MOP_OFFLOAD_ARCH", "gfx950")
 

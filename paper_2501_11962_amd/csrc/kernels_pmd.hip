@@ -6,6 +6,8 @@
 //   [veff_grad on the new R: G and V_eff]
 //   k_pmd_post  B (half kick with the new G) and per-block kinetic-energy partials
 //   k_reduce_ke deterministic FP64 sum of the partials, per path
+// With a metadynamics bias the gradient of each step includes the bias (kernels_bias.hip),
+// added after the V_eff gradient and before the second half kick.
 // With gamma = 0 (c1 = 1, c2 = 0) the O part is skipped and the step is velocity
 // Verlet, the constant-energy integrator of appendix A.2; gamma > 0 is the Langevin
 // thermostat of the constant-temperature runs.  All FP64, elementwise, HBM-bound:
@@ -126,7 +128,7 @@ __global__ void __launch_bounds__(EWB) k_pmd_post(const SegDev* __restrict__ seg
 // One block per path: kinetic energy, and V_eff of the step from the reduction slot.
 __global__ void __launch_bounds__(EWB) k_reduce_ke(const SegDev* __restrict__ segs, Launch L,
                                                    char* __restrict__ ws, double* __restrict__ out,
-                                                   int stride) {
+                                                   int stride, int has_bias) {
     __shared__ double sh[EWB / 64];
     const int p = blockIdx.x;
     const SegDev& sg = segs[p];
@@ -139,6 +141,10 @@ __global__ void __launch_bounds__(EWB) k_reduce_ke(const SegDev* __restrict__ se
         double* o = out + (size_t)sg.vidx * stride;
         o[0] = wsp<const double>(ws, sg.o_eres)[0];
         o[1] = s;
+        if (!has_bias) {
+            o[2] = 0.0;
+            o[3] = 0.0;
+        }
     }
 }
 
@@ -158,7 +164,7 @@ void run_pmd_pre(const SegDev* dsegs, const SegDev* hsegs, const Launch& base, d
 
 void run_pmd_post(const SegDev* dsegs, const SegDev* hsegs, const Launch& base, double* V,
                   const double* G, const PmdCoef& pc, char* ws, double* energies, int stride,
-                  hipStream_t st) {
+                  int has_bias, hipStream_t st) {
     Launch L = base;
     L.pf[0] = 0;
     for (int p = 0; p < base.nseg; ++p) L.pf[p + 1] = L.pf[p] + base.N[p] * hsegs[p].bpb;
@@ -166,7 +172,7 @@ void run_pmd_post(const SegDev* dsegs, const SegDev* hsegs, const Launch& base, 
     hipLaunchKernelGGL(k_pmd_post, dim3(L.pf[L.nseg]), dim3(EWB), 0, st, dsegs, L, V, G, pc, ws);
     if (energies)
         hipLaunchKernelGGL(k_reduce_ke, dim3(base.nseg), dim3(EWB), 0, st, dsegs, base, ws,
-                           energies, stride);
+                           energies, stride, has_bias);
 }
 
 }  // namespace mop

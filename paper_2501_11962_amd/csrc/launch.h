@@ -34,12 +34,19 @@ void run_finalize_hvp(const SegDev* dsegs, const SegDev* hsegs, const Launch& ba
                       const CallPtrs& cp, hipStream_t st);
 void run_status_clear(int* status, hipStream_t st);
 
+// Metadynamics bias: adds its gradient to G (if non-null), writes {V_bias, S} to out (if
+// non-null) and, with deposit, appends a Gaussian at S.
+void run_bias(const BiasDev& bd, const double* R, int N, int Q, double* G, double* out,
+              int deposit, int* status, hipStream_t st);
+void run_bias_reset(const BiasDev& bd, hipStream_t st);
+
 // Path integrator: the parts of one B A O A B step around the gradient evaluation.
 void run_pmd_pre(const SegDev* dsegs, const SegDev* hsegs, const Launch& base, double* R, double* V,
                  const double* G, const PmdCoef& pc, uint64_t step, hipStream_t st);
-// energies (device, or null): {V_eff, kinetic} of path p at energies + p * stride.
+// energies (device, or null): {V_eff, kinetic} of path p at energies + p * stride, and,
+// unless has_bias, zeros for the bias columns {V_bias, S} that follow.
 void run_pmd_post(const SegDev* dsegs, const SegDev* hsegs, const Launch& base, double* V,
                   const double* G, const PmdCoef& pc, char* ws, double* energies, int stride,
-                  hipStream_t st);
+                  int has_bias, hipStream_t st);
 
 }  // namespace mop

@@ -47,6 +47,13 @@ struct mop_plan_s {
     size_t ws_bytes;
 };
 
+struct mop_bias_s {
+    mop_plan plan;
+    BiasDev dev;
+    int stride;
+    std::vector<void*> allocs;
+};
+
 struct mop_batch_s {
     mop_ctx ctx;
     int P;
@@ -630,10 +637,112 @@ int veff_grad_timed(mop_plan plan, const double* R, int32_t N, double* G, double
     return rc;
 }
 
-int pmd_step(mop_plan plan, double* R, double* V, double* G, int32_t N,
+int mop_bias_create(mop_plan plan, const mop_bias_desc* d, mop_bias* out) {
+    if (!plan || !d || !out) return MOP_EINVAL;
+    *out = nullptr;
+    const int Q = plan->hseg.s.Q;
+    if (d->nA < 1 || d->nB < 1 || !d->groupA || !d->groupB) return MOP_EINVAL;
+    if (!(d->sigma > 0.0) || !(d->height >= 0.0) || d->stride < 1 || d->max_gaussians < 1)
+        return MOP_EINVAL;
+    if (!(d->bias_factor == 0.0 || d->bias_factor > 1.0)) return MOP_EINVAL;
+    if (d->bias_factor > 1.0 && !(d->kT > 0.0)) return MOP_EINVAL;
+    std::vector<char> seen(Q, 0);
+    for (int k = 0; k < d->nA + d->nB; ++k) {
+        const int i = k < d->nA ? d->groupA[k] : d->groupB[k - d->nA];
+        if (i < 0 || i >= Q || seen[i]) return MOP_EINVAL;  // in range, groups disjoint
+        seen[i] = 1;
+    }
+    if (hipSetDevice(plan->sys->ctx->device) != hipSuccess) return MOP_EHIP;
+    mop_bias b = new (std::nothrow) mop_bias_s;
+    if (!b) return MOP_ENOMEM;
+    b->plan = plan;
+    b->stride = d->stride;
+    BiasDev& bd = b->dev;
+    std::memset(&bd, 0, sizeof(bd));
+    bd.nA = d->nA;
+    bd.nB = d->nB;
+    bd.minv = plan->sys->dev.minv;
+    for (int a = 0; a < 3; ++a) bd.L[a] = plan->sys->box[a];
+    bd.sigma = d->sigma;
+    bd.height = d->height;
+    bd.bias_factor = d->bias_factor;
+    bd.kT = d->kT;
+    bd.capacity = d->max_gaussians;
+    auto dalloc = [&](void** p, size_t bytes) {
+        if (hipMalloc(p, bytes) != hipSuccess) return MOP_ENOMEM;
+        b->allocs.push_back(*p);
+        return MOP_OK;
+    };
+    int e = 0;
+    void *pa = nullptr, *pb = nullptr, *pc = nullptr, *ph = nullptr, *pn = nullptr;
+    if (!e) e = dalloc(&pa, sizeof(int) * d->nA);
+    if (!e) e = dalloc(&pb, sizeof(int) * d->nB);
+    if (!e) e = dalloc(&pc, sizeof(double) * d->max_gaussians);
+    if (!e) e = dalloc(&ph, sizeof(double) * d->max_gaussians);
+    if (!e) e = dalloc(&pn, sizeof(int));
+    if (!e && (hipMemcpy(pa, d->groupA, sizeof(int) * d->nA, hipMemcpyHostToDevice) != hipSuccess ||
+               hipMemcpy(pb, d->groupB, sizeof(int) * d->nB, hipMemcpyHostToDevice) != hipSuccess ||
+               hipMemset(pn, 0, sizeof(int)) != hipSuccess))
+        e = MOP_EHIP;
+    if (e) {
+        mop_bias_destroy(b);
+        return e;
+    }
+    bd.A = static_cast<const int*>(pa);
+    bd.B = static_cast<const int*>(pb);
+    bd.centers = static_cast<double*>(pc);
+    bd.heights = static_cast<double*>(ph);
+    bd.count = static_cast<int*>(pn);
+    *out = b;
+    return MOP_OK;
+}
+
+void mop_bias_destroy(mop_bias b) {
+    if (!b) return;
+    for (void* p : b->allocs) (void)hipFree(p);
+    delete b;
+}
+
+int mop_bias_reset(mop_bias b) {
+    if (!b) return MOP_EINVAL;
+    run_bias_reset(b->dev, b->plan->sys->ctx->stream);
+    return finish(b->plan->sys->ctx);
+}
+
+int mop_bias_apply(mop_bias b, const double* R, int32_t N, double* G, double* out,
+                   int32_t deposit, void* ws) {
+    if (!b || !R || !ws) return MOP_EINVAL;
+    if (N < 1) return MOP_EINVAL;
+    if (N > b->plan->max_beads) return MOP_ESIZE;
+    run_bias(b->dev, R, N, b->plan->hseg.s.Q, G, out, deposit ? 1 : 0, static_cast<int*>(ws),
+             b->plan->sys->ctx->stream);
+    return finish(b->plan->sys->ctx);
+}
+
+int mop_bias_history(mop_bias b, int32_t* count, double* centers, double* heights,
+                     int32_t capacity) {
+    if (!b || !count) return MOP_EINVAL;
+    hipStream_t st = b->plan->sys->ctx->stream;
+    if (hipStreamSynchronize(st) != hipSuccess) return MOP_EHIP;
+    int n = 0;
+    if (hipMemcpy(&n, b->dev.count, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
+        return MOP_EHIP;
+    *count = n;
+    const int m = std::min(n, std::max(capacity, 0));
+    if (m > 0 && centers &&
+        hipMemcpy(centers, b->dev.centers, sizeof(double) * m, hipMemcpyDeviceToHost) != hipSuccess)
+        return MOP_EHIP;
+    if (m > 0 && heights &&
+        hipMemcpy(heights, b->dev.heights, sizeof(double) * m, hipMemcpyDeviceToHost) != hipSuccess)
+        return MOP_EHIP;
+    return MOP_OK;
+}
+
+int pmd_step(mop_plan plan, mop_bias bias, double* R, double* V, double* G, int32_t N,
              const mop_pmd_params* prm, uint64_t step0, int32_t nsteps, double* energies,
              void* ws) {
     if (!plan || !R || !V || !G || !prm || !ws) return MOP_EINVAL;
+    if (bias && bias->plan != plan) return MOP_EINVAL;
     if (N < 1 || nsteps < 1) return MOP_EINVAL;
     if (N > plan->max_beads) return MOP_ESIZE;
     if (!(prm->tau > 0.0) || !(prm->gamma >= 0.0) || !(prm->kT >= 0.0)) return MOP_EINVAL;
@@ -650,11 +759,15 @@ int pmd_step(mop_plan plan, double* R, double* V, double* G, int32_t N,
     cp.G = G;
     const Launch L = one_path(N, N > 1 ? N - 1 : 1);
     for (int32_t k = 0; k < nsteps; ++k) {
-        double* ek = energies ? energies + 2 * (size_t)k : nullptr;
-        run_pmd_pre(plan->dseg, &plan->hseg, L, R, V, G, pc, step0 + (uint64_t)k, st);
+        const uint64_t step = step0 + (uint64_t)k;
+        double* ek = energies ? energies + 4 * (size_t)k : nullptr;
+        run_pmd_pre(plan->dseg, &plan->hseg, L, R, V, G, pc, step, st);
         cp.veff = nullptr;
         path_sequence(plan->dseg, &plan->hseg, L, cp, true, 0, plan->waves, plan->newton3, st);
-        run_pmd_post(plan->dseg, &plan->hseg, L, V, G, pc, cp.ws, ek, 2, st);
+        if (bias)
+            run_bias(bias->dev, R, N, plan->hseg.s.Q, G, ek ? ek + 2 : nullptr,
+                     step % (uint64_t)bias->stride == 0 ? 1 : 0, cp.status, st);
+        run_pmd_post(plan->dseg, &plan->hseg, L, V, G, pc, cp.ws, ek, 4, bias ? 1 : 0, st);
     }
     return finish(plan->sys->ctx);
 }

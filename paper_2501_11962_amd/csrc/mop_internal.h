@@ -103,6 +103,23 @@ struct PmdCoef {
     uint64_t seed;        // key of the normal deviates
 };
 
+// Metadynamics bias on the end-to-end variable (device state of one mop_bias).
+struct BiasDev {
+    const int* A;         // [nA] atoms of group A
+    const int* B;         // [nB] atoms of group B
+    int nA, nB;
+    const double* minv;   // [Q] 1 / m of the system
+    double L[3];
+    double sigma;         // Gaussian width in S (nm)
+    double height;        // initial height (kJ/mol)
+    double bias_factor;   // > 1: well-tempered; 0: standard
+    double kT;
+    double* centers;      // [capacity]
+    double* heights;      // [capacity]
+    int* count;           // deposited Gaussians
+    int capacity;
+};
+
 // Pointers of one call (device).
 struct CallPtrs {
     const double* R;      // bead coordinates, packed paths
