@@ -64,24 +64,33 @@ __global__ void __launch_bounds__(EWB) k_bin_count(const SegDev* __restrict__ se
     wsp<int>(ws, sg.o_rank)[(size_t)b * Q + i] = rank;
 }
 
-// Exclusive scan of the z bins of each column; column totals.
+// Exclusive scan of the z bins of each column; column totals.  One wave per column:
+// each lane sums a run of consecutive bins, a wave scan places the runs.
 __global__ void __launch_bounds__(EWB) k_bin_colscan(const SegDev* __restrict__ segs, Launch L, char* ws) {
     const int blk = blockIdx.x;
     const int p = find_seg(L, blk);
     const SegDev& sg = segs[p];
-    const int t = (blk - L.pf[p]) * EWB + threadIdx.x;
+    const int t = (blk - L.pf[p]) * (EWB / 64) + (threadIdx.x >> 6);  // column of this wave
+    const int lane = threadIdx.x & 63;
     const int ncol = sg.s.ncol, nzb = sg.s.nzb;
     if (t >= L.nb[p] * ncol) return;
     const int b = t / ncol, col = t - b * ncol;
     const int* cnt = wsp<const int>(ws, sg.o_bincnt) + ((size_t)b * ncol + col) * nzb;
     int* off = wsp<int>(ws, sg.o_binoff) + ((size_t)b * ncol + col) * (nzb + 1);
-    int run = 0;
-    for (int z = 0; z < nzb; ++z) {
+    const int per = (nzb + 63) >> 6;
+    const int z0 = min(lane * per, nzb), z1 = min(z0 + per, nzb);
+    int sum = 0;
+    for (int z = z0; z < z1; ++z) sum += cnt[z];
+    const int incl = wave_incl_scan(sum);
+    int run = incl - sum;
+    for (int z = z0; z < z1; ++z) {
         off[z] = run;
         run += cnt[z];
     }
-    off[nzb] = run;
-    wsp<int>(ws, sg.o_colcnt)[(size_t)b * ncol + col] = run;
+    if (lane == 63) {
+        off[nzb] = incl;
+        wsp<int>(ws, sg.o_colcnt)[(size_t)b * ncol + col] = incl;
+    }
 }
 
 // Exclusive scan of the padded (multiple of 8) column counts of one bead per block.
@@ -213,7 +222,11 @@ void run_binning(const SegDev* dsegs, const SegDev* hsegs, const Launch& base, c
     Lc.pf[0] = 0;
     for (int p = 0; p < base.nseg; ++p)
         Lc.pf[p + 1] = Lc.pf[p] + (base.nb[p] * hsegs[p].s.ncol + EWB - 1) / EWB;
-    hipLaunchKernelGGL(k_bin_colscan, dim3(Lc.pf[base.nseg]), dim3(EWB), 0, st, dsegs, Lc, ws);
+    Launch Lw = base;  // one wave per column
+    Lw.pf[0] = 0;
+    for (int p = 0; p < base.nseg; ++p)
+        Lw.pf[p + 1] = Lw.pf[p] + (base.nb[p] * hsegs[p].s.ncol + EWB / 64 - 1) / (EWB / 64);
+    hipLaunchKernelGGL(k_bin_colscan, dim3(Lw.pf[base.nseg]), dim3(EWB), 0, st, dsegs, Lw, ws);
     Launch Lb = base;
     Lb.pf[0] = 0;
     for (int p = 0; p < base.nseg; ++p) Lb.pf[p + 1] = Lb.pf[p] + base.nb[p];

@@ -47,10 +47,11 @@ namespace mop {
 // Ring fields (one LDS array [field][entry] per wave; ints stored as float bits).
 constexpr int F_X = 0, F_Y = 1, F_Z = 2, F_Q = 3, F_K = 4, F_T = 5, F_S = 6, F_J = 7;
 
-// Table entries per type pair: force kernels keep {a12, a6, csf, e0lj} and
-// {b12, b6, c12, c6} interleaved (the second for energies); the Hessian kernel one.
+// Table entries per type pair in LDS, 16 bytes apart: the force kernels keep
+// {a12, a6, csf, e0lj} for the nt^2 pairs followed by {b12, b6, c12, c6} (energies);
+// the Hessian kernel keeps {a12, a6, csf, 0.75 a12}.
 template <int MODE>
-constexpr int TAB_STRIDE = MODE == 1 ? 1 : 2;
+constexpr int TAB_COPIES = MODE == 1 ? 1 : 2;
 
 template <int MODE, int N3>
 struct Fields {
@@ -76,6 +77,7 @@ struct PairK {
 // at the type-table row of atom i.
 template <int MODE, bool EX, bool WANTE, bool T_OUT>
 __device__ __forceinline__ void pair_term(const IAtom& I, const PairK& P, const float4* tabrow,
+                                          int ntab,
                                           float jx, float jy, float jz,
                                           float qj, int kj, int tj, float vjx, float vjy,
                                           float vjz, bool valid, float& ax, float& ay,
@@ -100,7 +102,7 @@ __device__ __forceinline__ void pair_term(const IAtom& I, const PairK& P, const 
     const float rinv2 = rinv * rinv;
     const float rinv6 = rinv2 * rinv2 * rinv2;
     const float rinv3 = rinv2 * rinv;
-    const float4 T = tabrow[TAB_STRIDE<MODE> * tj];
+    const float4 T = tabrow[tj];
     const float qq = I.q * qj;
     const float C1 = fmaf(qq, P.crf1, T.z);
     const float G6 = fmaf(T.x, rinv6, T.y);
@@ -123,7 +125,7 @@ __device__ __forceinline__ void pair_term(const IAtom& I, const PairK& P, const 
             az = fmaf(g, dz, az);
         }
         if (WANTE) {
-            const float4 T2 = tabrow[2 * tj + 1];
+            const float4 T2 = tabrow[ntab + tj];
             const float r = r2s * rinv;
             float e = fmaf(T2.z, rinv6, -T2.w) * rinv6;
             const float erf = rinv + P.krf * r2s - P.crf + P.e0rf + P.crf1 * r;
@@ -172,16 +174,16 @@ __global__ void __launch_bounds__(64 * PW) k_pair(const SegDev* __restrict__ seg
     const SegDev* __restrict__ sg = segs + p;
     const int nt = sg->s.nt;
     const int ntm = L.ntmax;
-    constexpr int TS = TAB_STRIDE<MODE>;
+    constexpr int TC = TAB_COPIES<MODE>;
     float4* s_tab = s_dyn;
-    float* s_ring = reinterpret_cast<float*>(s_dyn + TS * ntm * ntm);
+    float* s_ring = reinterpret_cast<float*>(s_dyn + TC * ntm * ntm);
     int* s_cl = reinterpret_cast<int*>(s_ring + PW * NF * RING);
     for (int t = threadIdx.x; t < nt * nt; t += 64 * PW) {
         if (MODE == 1) {
             s_tab[t] = sg->s.tabh[t];
         } else {
-            s_tab[2 * t] = sg->s.tab[t];
-            s_tab[2 * t + 1] = sg->s.tab2[t];
+            s_tab[t] = sg->s.tab[t];
+            s_tab[nt * nt + t] = sg->s.tab2[t];
         }
     }
     __syncthreads();  // the only block barrier: waves are independent from here on
@@ -231,7 +233,8 @@ __global__ void __launch_bounds__(64 * PW) k_pair(const SegDev* __restrict__ seg
     I.q = __uint_as_float(ui.w);
     I.key2 = mi.x + 2;
     I.tiN = mi.y * nt;
-    const float4* tabrow = s_tab + TS * I.tiN;
+    const float4* tabrow = s_tab + I.tiN;
+    const int ntab = nt * nt;
     I.ux = ui.x;
     I.uy = ui.y;
     I.uz = ui.z;
@@ -296,6 +299,10 @@ __global__ void __launch_bounds__(64 * PW) k_pair(const SegDev* __restrict__ seg
     // z window of candidate atoms of a column whose rectangle is (gx, gy) away from the
     // bounding box: |z - box| < sqrt(rcs^2 - gx^2 - gy^2), in z bins (per lane)
     const float Lz = sg->s.Lf[2];
+    // reciprocals instead of divisions: a z bound off by one fixed-point unit, or a
+    // column image chosen either way at an exact half-box tie (both images then lie at
+    // the same distance), changes no test
+    const float isz = 1.0f / sz;
     auto zwindow = [&](float g2, bool& fullz, bool& zwrap, int& zb0, int& zb1)
                        __attribute__((always_inline)) {
         const float hz = sqrtf(fmaxf(rcs2 - g2, 0.0f));
@@ -304,8 +311,8 @@ __global__ void __launch_bounds__(64 * PW) k_pair(const SegDev* __restrict__ seg
         zb1 = nzb - 1;
         zwrap = false;
         if (!fullz) {
-            const long long dlo = (long long)floorf((loz - hz) / sz);
-            const long long dhi = (long long)ceilf((hiz + hz) / sz);
+            const long long dlo = (long long)floorf((loz - hz) * isz);
+            const long long dhi = (long long)ceilf((hiz + hz) * isz);
             const uint32_t zlo = ucz + (uint32_t)dlo;
             const uint32_t zhi = ucz + (uint32_t)dhi;
             zb0 = fixed_bin(zlo, nzb);
@@ -318,6 +325,7 @@ __global__ void __launch_bounds__(64 * PW) k_pair(const SegDev* __restrict__ seg
     const float bcy = 0.5f * (loy + hiy), bhy = 0.5f * (hiy - loy);
     const float xref = (float)ucx * sx, yref = (float)ucy * sy;
     const float Lx = sg->s.Lf[0], Ly = sg->s.Lf[1];
+    const float iLx = 1.0f / Lx, iLy = 1.0f / Ly;
     const float cwx = sg->s.cw[0], cwy = sg->s.cw[1];
 
     float ax = 0.f, ay = 0.f, az = 0.f;
@@ -366,17 +374,17 @@ __global__ void __launch_bounds__(64 * PW) k_pair(const SegDev* __restrict__ seg
         const float qj = __uint_as_float(uj.w);
         if (exact) {
             if (wantE)
-                pair_term<MODE, true, true, false>(I, P, tabrow, jx, jy, jz, qj, mj.x, mj.y, vjx,
+                pair_term<MODE, true, true, false>(I, P, tabrow, ntab, jx, jy, jz, qj, mj.x, mj.y, vjx,
                                             vjy, vjz, vj, ax, ay, az, tx, ty, tz, en);
             else
-                pair_term<MODE, true, false, false>(I, P, tabrow, jx, jy, jz, qj, mj.x, mj.y, vjx,
+                pair_term<MODE, true, false, false>(I, P, tabrow, ntab, jx, jy, jz, qj, mj.x, mj.y, vjx,
                                              vjy, vjz, vj, ax, ay, az, tx, ty, tz, en);
         } else {
             if (wantE)
-                pair_term<MODE, false, true, false>(I, P, tabrow, jx, jy, jz, qj, mj.x, mj.y, vjx,
+                pair_term<MODE, false, true, false>(I, P, tabrow, ntab, jx, jy, jz, qj, mj.x, mj.y, vjx,
                                              vjy, vjz, vj, ax, ay, az, tx, ty, tz, en);
             else
-                pair_term<MODE, false, false, false>(I, P, tabrow, jx, jy, jz, qj, mj.x, mj.y, vjx,
+                pair_term<MODE, false, false, false>(I, P, tabrow, ntab, jx, jy, jz, qj, mj.x, mj.y, vjx,
                                               vjy, vjz, vj, ax, ay, az, tx, ty, tz, en);
         }
         eacc += 0.5f * en;
@@ -421,7 +429,7 @@ __global__ void __launch_bounds__(64 * PW) k_pair(const SegDev* __restrict__ seg
                 }
             }
             float tx, ty, tz, en = 0.f;
-            pair_term<MODE, EX, WE, N3 == 1>(I, P, tabrow, jxv, jyv, jzv, qjv, kj, tjv, vjx, vjy,
+            pair_term<MODE, EX, WE, N3 == 1>(I, P, tabrow, ntab, jxv, jyv, jzv, qjv, kj, tjv, vjx, vjy,
                                              vjz, valid, ax, ay, az, tx, ty, tz, en);
             if (WE) eacc += N3 ? en : 0.5f * en;
             if (N3) {
@@ -597,18 +605,20 @@ __global__ void __launch_bounds__(64 * PW) k_pair(const SegDev* __restrict__ seg
         int a0 = 0, a1 = 0, b0 = 0, b1 = 0;
         if (k < nst) {
             const int ox = k / wy, oy = k - ox * wy;
+            // stencil half widths are below the column counts (else the stencil spans
+            // every column), so one wrap suffices
             int jxc = sg->s.allx ? ox : cx + ox - sg->s.rx;
             int jyc = sg->s.ally ? oy : cy + oy - sg->s.ry;
-            jxc = ((jxc % ncx) + ncx) % ncx;
-            jyc = ((jyc % ncy) + ncy) % ncy;
+            jxc += jxc < 0 ? ncx : (jxc >= ncx ? -ncx : 0);
+            jyc += jyc < 0 ? ncy : (jyc >= ncy ? -ncy : 0);
             float dxc = ((float)jxc + 0.5f) * cwx - xref;
-            dxc -= Lx * rintf(dxc / Lx);
+            dxc -= Lx * rintf(dxc * iLx);
             dxc -= bcx;
-            dxc -= Lx * rintf(dxc / Lx);
+            dxc -= Lx * rintf(dxc * iLx);
             float dyc = ((float)jyc + 0.5f) * cwy - yref;
-            dyc -= Ly * rintf(dyc / Ly);
+            dyc -= Ly * rintf(dyc * iLy);
             dyc -= bcy;
-            dyc -= Ly * rintf(dyc / Ly);
+            dyc -= Ly * rintf(dyc * iLy);
             const float gx = fmaxf(0.0f, fabsf(dxc) - 0.5f * cwx - bhx);
             const float gy = fmaxf(0.0f, fabsf(dyc) - 0.5f * cwy - bhy);
             const int col = jxc * ncy + jyc;
@@ -733,7 +743,7 @@ static void launch_pair_t(const SegDev* dsegs, const SegDev* hsegs, const Launch
     const int nblk = L.pf[base.nseg];
     if (nblk == 0) return;
     const int grid = ((nblk + 7) / 8) * 8;
-    const size_t lds = TAB_STRIDE<MODE> * (size_t)L.ntmax * L.ntmax * sizeof(float4) +
+    const size_t lds = TAB_COPIES<MODE> * (size_t)L.ntmax * L.ntmax * sizeof(float4) +
                        (size_t)PW * Fields<MODE, N3>::NF * RING * sizeof(float) +
                        (size_t)PW * CLIST * sizeof(int);
     hipLaunchKernelGGL((k_pair<MODE, PW, N3>), dim3(grid), dim3(64 * PW), lds, st, dsegs, L, ws,

@@ -137,15 +137,35 @@ __device__ double pair_energy_of_bead(const SegDev& sg, char* ws, int b, int t0,
     const int nslots = wsp<const int>(ws, sg.o_colstart)[(size_t)b * (ncol + 1) + ncol];
     const int ncl = nslots / CLUSTER;
     const double* ep = wsp<const double>(ws, sg.o_epart) + (size_t)b * sg.s.cpb;
-    double e = 0.0;
-    for (int c = t0; c < ncl; c += stride) e += ep[c];
-    return e;
+    double e0 = 0.0, e1 = 0.0;
+    int c = t0;
+    for (; c + stride < ncl; c += 2 * stride) {  // two independent chains in flight
+        e0 += ep[c];
+        e1 += ep[c + stride];
+    }
+    if (c < ncl) e0 += ep[c];
+    return e0 + e1;
+}
+
+// Block-wide sum over RVB threads (result valid in thread 0).
+constexpr int RVB = 1024;
+__device__ __forceinline__ double block_sum_rvb(double v, double* sh) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    __syncthreads();
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < RVB / 64; ++k) s += sh[k];
+    return s;
 }
 
 // One block per path: V_eff = U(R^1) + E_spring.
-__global__ void __launch_bounds__(EWB) k_reduce_veff(const SegDev* __restrict__ segs, Launch L,
+__global__ void __launch_bounds__(RVB) k_reduce_veff(const SegDev* __restrict__ segs, Launch L,
                                                      CallPtrs cp) {
-    __shared__ double sh[EWB / 64];
+    __shared__ double sh[RVB / 64];
     const int p = blockIdx.x;
     const SegDev& sg = segs[p];
     char* ws = cp.ws;
@@ -153,11 +173,11 @@ __global__ void __launch_bounds__(EWB) k_reduce_veff(const SegDev* __restrict__ 
     const int nbr = N > 1 ? N - 1 : 1;
     const double* rp = wsp<const double>(ws, sg.o_rpart);
     double es = 0.0, eb = 0.0;
-    for (int k = threadIdx.x; k < nbr * sg.bpb; k += EWB) es += rp[2 * k];
-    for (int k = threadIdx.x; k < sg.bpb; k += EWB) eb += rp[2 * k + 1];
-    const double ep = pair_energy_of_bead(sg, ws, 0, threadIdx.x, EWB);
-    const double S_es = block_sum(es, sh);
-    const double S_u = block_sum(eb + ep, sh);
+    for (int k = threadIdx.x; k < nbr * sg.bpb; k += RVB) es += rp[2 * k];
+    for (int k = threadIdx.x; k < sg.bpb; k += RVB) eb += rp[2 * k + 1];
+    const double ep = pair_energy_of_bead(sg, ws, 0, threadIdx.x, RVB);
+    const double S_es = block_sum_rvb(es, sh);
+    const double S_u = block_sum_rvb(eb + ep, sh);
     if (threadIdx.x == 0) {
         double* er = wsp<double>(ws, sg.o_eres);
         er[0] = S_u + S_es;
@@ -282,7 +302,7 @@ void run_assemble(const SegDev* dsegs, const SegDev* hsegs, const Launch& base, 
 void run_reduce_veff(const SegDev* dsegs, const SegDev* hsegs, const Launch& base,
                      const CallPtrs& cp, hipStream_t st) {
     (void)hsegs;
-    hipLaunchKernelGGL(k_reduce_veff, dim3(base.nseg), dim3(EWB), 0, st, dsegs, base, cp);
+    hipLaunchKernelGGL(k_reduce_veff, dim3(base.nseg), dim3(RVB), 0, st, dsegs, base, cp);
 }
 
 void run_finalize_forces(const SegDev* dsegs, const SegDev* hsegs, const Launch& base,
