@@ -184,6 +184,53 @@ def bench_batch(args, mop, ctx, log):
     return out
 
 
+def bench_pmd(args, mop, ctx, plan, system, Rt, ms_grad, log):
+    """Path dynamics on the same workload: Langevin B A O A B steps (gamma = 250 / ps,
+    300 K) with the metadynamics bias on the end-to-end variable of eq. (8).  The
+    synthetic membrane is not relaxed (it keeps overlapping atoms), so the step is
+    0.01 fs to keep the run finite; the cost of a step does not depend on it.  Groups: one bonded 50-atom chain (ligand-sized) and the atoms within
+    1.2 nm of its first atom (pocket-sized).  Reports ms per step and what the
+    integrator and the bias add to one veff_grad call."""
+    import torch
+    X = np.asarray(system["x"])
+    L = np.asarray(system["box"])
+    bonds = np.asarray(system["bonds"]).reshape(-1, 2)
+    a0 = int(bonds[0, 0])
+    mol = np.asarray(system["mol"])
+    d = X - X[a0]
+    d -= L * np.rint(d / L)
+    r2 = (d * d).sum(1)
+    A = np.nonzero((mol == mol[a0]) & (r2 < 0.8 ** 2))[0]      # compact: < half the box
+    B = np.setdiff1d(np.nonzero(r2 < 1.2 ** 2)[0], A)
+    kT = 0.0083144626 * 300.0
+    bias = mop.Bias(plan, A, B, 0.02, 1.0, 10.0, kT, stride=5, max_gaussians=1 << 16)
+    R = Rt.clone()
+    V = torch.zeros_like(R)
+    G, _ = mop.veff_grad(plan, R)
+    bias.apply(R, G)
+    steps = max(args.steps // 2, 5)
+    tau = 1e-5
+    mop.pmd_step(plan, R, V, G, tau, 2, 250.0, kT, seed=7, step0=0, bias=bias)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    E = mop.pmd_step(plan, R, V, G, tau, steps, 250.0, kT, seed=7, step0=2, bias=bias)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    st = plan.status()
+    Q, N = system["Q"], Rt.shape[0]
+    out = dict(workload=f"Langevin path dynamics with the end-to-end bias: groups of {len(A)} "
+                        f"and {len(B)} atoms, deposit every 5 steps, tau 0.01 fs",
+               ms_per_step=ms, value=Q * N / (ms * 1e-3), unit="atom·beads/s",
+               overhead_vs_veff_grad_ms=ms - ms_grad, steps=steps,
+               gaussians=len(bias.history()[0]), device_status=st,
+               energies_finite=bool(torch.isfinite(E).all()))
+    log(f"[bench] pmd: {ms:.3f} ms/step (veff_grad {ms_grad:.3f}), status {st}")
+    plan.clear_status()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -196,6 +243,7 @@ def main():
     ap.add_argument("--fd-h", type=float, default=1e-4)
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-pmd", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (a known-size "
                          "kernel that scales HBM byte counters read by a profiler)")
@@ -357,6 +405,8 @@ def main():
             acc["fd_best"] = min(acc["fd_by_h_nm"].values())
         out["accuracy_relL2"] = acc
         log(f"[bench] accuracy: {json.dumps(acc)}")
+    if not args.no_pmd:
+        out["pmd"] = bench_pmd(args, mop, ctx, plan, system, Rt, ms_eager, log)
     if not args.no_batch:
         out["batch"] = bench_batch(args, mop, ctx, log)
     print(json.dumps(out), flush=True)
