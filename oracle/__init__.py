@@ -8,6 +8,12 @@ Contents
     potential.py  U, F = -grad U and the Hessian-vector product H v of the short-range
                   potential (shifted-force Lennard-Jones + reaction field, harmonic
                   bonds, 1-2/1-3 exclusions), by brute force over all minimum-image pairs.
+    ewald.py      The Ewald sum of periodic Coulomb interactions (real, reciprocal, self,
+                  excluded-pair and background terms), the definition PME approximates.
+    pme.py        Smooth particle-mesh Ewald: spline weights, charge grid, influence
+                  function, energy, forces and the exact Hessian-vector product.
+                  potential.Model uses it (with the Ewald real-space pair term) for
+                  systems with elec = "pme".
     path.py       The effective potential of eq. (3), its exact gradient, the
                   finite-difference Hessian term of eq. (5), and a literal evaluation of
                   the effective forces of eqs. (5)-(7).

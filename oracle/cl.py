@@ -65,6 +65,9 @@ class CellModel(Model):
 
     def __init__(self, system, nthreads=0):
         super().__init__(system)
+        if self.elec != "rf":
+            raise NotImplementedError("the C cell-list oracle covers reaction-field "
+                                      "electrostatics only; use potential.Model for PME")
         self.nthreads = int(nthreads)
         Q = self.Q
         ex = self.excluded

@@ -21,6 +21,16 @@ out from its textbook definition:
 Excluded pairs: atoms one or two bonds apart (1-2 and 1-3 neighbours in the bond
 graph), from both LJ and RF.
 
+Particle-mesh Ewald electrostatics (system key elec = "pme"; the paper's own runs use
+PME, Appendix A.1) replaces phi_RF by the Ewald real-space term and adds the
+reciprocal, self, background and excluded-pair terms (ewald.py, pme.py):
+
+  phi_real(r) = f q_i q_j erfc(beta r)/r, shifted-force at r_c like the other pair terms
+              (erfc(beta r_c) = ewald_rtol fixes beta)
+  excluded pairs within r_c:  -f q_i q_j erf(beta r)/r   (no cut-off modifier)
+  + E_rec (smooth PME, order pme_order, grid pme_grid) - f beta/sqrt(pi) sum q^2
+  - f pi (sum q)^2 / (2 V beta^2)
+
 Derivatives, for a pair with separation vector d = x_j - x_i and r = |d|:
   g = phi'(r)/r,   h = (phi''(r) - phi'(r)/r)/r^2
   F_i += g d,  F_j -= g d                                   (F = -grad U)
@@ -29,7 +39,11 @@ Derivatives, for a pair with separation vector d = x_j - x_i and r = |d|:
 """
 from __future__ import annotations
 
+import math
+
 import numpy as np
+from scipy.special import erf as _np_erf
+from scipy.special import erfc as _np_erfc
 
 F_ELEC = 138.935458  # kJ mol^-1 nm e^-2, electric conversion factor 1/(4 pi eps0)
 
@@ -67,6 +81,50 @@ def rf_d1(r, qq, krf, crf):
 
 def rf_d2(r, qq, krf, crf):
     return qq * (2.0 / r ** 3 + 2.0 * krf)
+
+
+def _erfc(x):
+    if isinstance(x, np.ndarray) or np.isscalar(x):
+        return _np_erfc(x)
+    import torch
+    return torch.special.erfc(x)
+
+
+def _exp(x):
+    if isinstance(x, np.ndarray) or np.isscalar(x):
+        return np.exp(x)
+    import torch
+    return torch.exp(x)
+
+
+def ewald_phi(r, qq, beta):
+    """Ewald real-space pair energy qq erfc(beta r)/r."""
+    return qq * _erfc(beta * r) / r
+
+
+def ewald_d1(r, qq, beta):
+    D = 2.0 * beta / math.sqrt(math.pi) * _exp(-(beta * r) ** 2)
+    return qq * (-_erfc(beta * r) / r ** 2 - D / r)
+
+
+def ewald_d2(r, qq, beta):
+    D = 2.0 * beta / math.sqrt(math.pi) * _exp(-(beta * r) ** 2)
+    return qq * (2.0 * _erfc(beta * r) / r ** 3 + D * (2.0 / r ** 2 + 2.0 * beta ** 2))
+
+
+def excl_phi(r, qq, beta):
+    """Excluded-pair correction -qq erf(beta r)/r = qq (erfc(beta r) - 1)/r."""
+    return qq * (_erfc(beta * r) - 1.0) / r
+
+
+def excl_d1(r, qq, beta):
+    D = 2.0 * beta / math.sqrt(math.pi) * _exp(-(beta * r) ** 2)
+    return qq * (-(_erfc(beta * r) - 1.0) / r ** 2 - D / r)
+
+
+def excl_d2(r, qq, beta):
+    D = 2.0 * beta / math.sqrt(math.pi) * _exp(-(beta * r) ** 2)
+    return qq * (2.0 * (_erfc(beta * r) - 1.0) / r ** 3 + D * (2.0 / r ** 2 + 2.0 * beta ** 2))
 
 
 def bond_phi(r, r0, kb):
@@ -113,6 +171,20 @@ class Model:
         self.mass = np.asarray(s["mass"], np.float64)
         self.dt, self.nu = float(s["dt"], ), float(s["nu"])
         self.excluded = self._exclusions()
+        self.elec = str(s.get("elec", "rf"))
+        if self.elec not in ("rf", "pme"):
+            raise ValueError("elec must be 'rf' or 'pme'")
+        self.pme = None
+        if self.elec == "pme":
+            from . import ewald
+            from .pme import PME
+            self.beta = ewald.beta_from_rtol(self.rc, float(s.get("ewald_rtol", 1e-5)))
+            self.pme = PME(self.box, s["pme_grid"], int(s.get("pme_order", 4)), self.beta,
+                           self.q, self.fq)
+            V = float(np.prod(self.box))
+            self.e_const = (-self.fq * self.beta / math.sqrt(math.pi) * float(np.sum(self.q ** 2))
+                            - self.fq * math.pi * float(np.sum(self.q)) ** 2
+                            / (2.0 * V * self.beta ** 2))
 
     def _exclusions(self):
         """Sorted codes i*Q + j (i < j) of pairs one or two bonds apart."""
@@ -170,10 +242,25 @@ class Model:
         if not isinstance(r, np.ndarray):
             c6, c12, qq = r.new_tensor(c6), r.new_tensor(c12), r.new_tensor(qq)
         rc = self.rc
-        phi = lj_phi(r, c6, c12) + rf_phi(r, qq, self.krf, self.crf)
-        phic = lj_phi(rc, c6, c12) + rf_phi(rc, qq, self.krf, self.crf)
-        d1c = lj_d1(rc, c6, c12) + rf_d1(rc, qq, self.krf, self.crf)
+        phi = lj_phi(r, c6, c12) + self._el_phi(r, qq)
+        phic = lj_phi(rc, c6, c12) + self._el_phi(rc, qq)
+        d1c = lj_d1(rc, c6, c12) + self._el_d1(rc, qq)
         return phi - phic - (r - rc) * d1c
+
+    def _el_phi(self, r, qq):
+        if self.elec == "pme":
+            return ewald_phi(r, qq, self.beta)
+        return rf_phi(r, qq, self.krf, self.crf)
+
+    def _el_d1(self, r, qq):
+        if self.elec == "pme":
+            return ewald_d1(r, qq, self.beta)
+        return rf_d1(r, qq, self.krf, self.crf)
+
+    def _el_d2(self, r, qq):
+        if self.elec == "pme":
+            return ewald_d2(r, qq, self.beta)
+        return rf_d2(r, qq, self.krf, self.crf)
 
     def pair_gh(self, r, i, j):
         """g = phi_sf'/r and h = (phi'' - phi_sf'/r)/r^2 for pairs (i, j)."""
@@ -181,12 +268,34 @@ class Model:
         c6, c12 = self.c6[ti, tj], self.c12[ti, tj]
         qq = self.fq * self.q[i] * self.q[j]
         rc = self.rc
-        d1 = lj_d1(r, c6, c12) + rf_d1(r, qq, self.krf, self.crf)
-        d1 = d1 - (lj_d1(rc, c6, c12) + rf_d1(rc, qq, self.krf, self.crf))
-        d2 = lj_d2(r, c6, c12) + rf_d2(r, qq, self.krf, self.crf)
+        d1 = lj_d1(r, c6, c12) + self._el_d1(r, qq)
+        d1 = d1 - (lj_d1(rc, c6, c12) + self._el_d1(rc, qq))
+        d2 = lj_d2(r, c6, c12) + self._el_d2(r, qq)
         g = d1 / r
         h = (d2 - g) / r ** 2
         return g, h
+
+    # -- PME: excluded pairs within the cut-off carry -f q_i q_j erf(beta r)/r ----------
+    def excluded_pairs(self, X):
+        """Excluded pairs (i < j) within r_c: (i, j, d), d = x_j - x_i (minimum image)."""
+        if not self.excluded.size:
+            z = np.zeros(0, np.int64)
+            return z, z, np.zeros((0, 3))
+        i = self.excluded // self.Q
+        j = self.excluded % self.Q
+        d = min_image(np.asarray(X, np.float64)[j] - np.asarray(X, np.float64)[i], self.box)
+        r2 = np.einsum("ak,ak->a", d, d)
+        keep = r2 < self.rc ** 2
+        return i[keep], j[keep], d[keep]
+
+    def _excl_terms(self, X):
+        i, j, d = self.excluded_pairs(X)
+        r = np.sqrt(np.einsum("ak,ak->a", d, d))
+        qq = self.fq * self.q[i] * self.q[j]
+        d1 = excl_d1(r, qq, self.beta)
+        g = d1 / r
+        h = (excl_d2(r, qq, self.beta) - g) / r ** 2
+        return i, j, d, r, qq, g, h
 
     def bond_vectors(self, X):
         b = self.bonds
@@ -204,6 +313,10 @@ class Model:
             bi, bj, bd = self.bond_vectors(X)
             br = np.sqrt(np.einsum("ak,ak->a", bd, bd))
             e += float(np.sum(bond_phi(br, self.bond_r0, self.bond_k)))
+        if self.pme is not None:
+            _, _, _, r, qq, _, _ = self._excl_terms(X)
+            e += float(np.sum(excl_phi(r, qq, self.beta)))
+            e += self.pme.energy(X) + self.e_const
         return e
 
     def forces(self, X):
@@ -223,6 +336,12 @@ class Model:
             f = bg[:, None] * bd
             np.add.at(F, bi, f)
             np.add.at(F, bj, -f)
+        if self.pme is not None:
+            ei, ej, ed, _, _, eg, _ = self._excl_terms(X)
+            f = eg[:, None] * ed
+            np.add.at(F, ei, f)
+            np.add.at(F, ej, -f)
+            F += self.pme.forces(X)
         return F
 
     def hvp(self, X, V):
@@ -241,6 +360,10 @@ class Model:
             bg = d1 / br
             bh = (bond_d2(br, self.bond_r0, self.bond_k) - bg) / br ** 2
             self._hvp_acc(out, bi, bj, bd, bg, bh, V)
+        if self.pme is not None:
+            ei, ej, ed, _, _, eg, eh = self._excl_terms(X)
+            self._hvp_acc(out, ei, ej, ed, eg, eh, V)
+            out += self.pme.hvp(X, V)
         return out
 
     @staticmethod

@@ -365,6 +365,32 @@ def tiny(Q=24, L=1.6, seed=7, rc=0.7, charges=True, bonds=True, ntypes=2, dt=DT_
                    rc=rc, dt=dt, nu=nu)
 
 
+def _smooth_at_least(n):
+    """Smallest integer >= n whose only prime factors are 2, 3, 5 and 7."""
+    k = max(int(n), 1)
+    while True:
+        m = k
+        for f in (2, 3, 5, 7):
+            while m % f == 0:
+                m //= f
+        if m == 1:
+            return k
+        k += 1
+
+
+def with_pme(system, spacing=0.12, order=4, rtol=1e-5, grid=None):
+    """Copy of a system switched to particle-mesh Ewald electrostatics (the paper's
+    standard-MD setting, Appendix A.1): real-space cut-off = the system's r_c, splitting
+    parameter from erfc(beta r_c) = rtol, B-spline order `order`, and a grid of at most
+    `spacing` nm per point (2,3,5,7-smooth sizes) unless `grid` is given."""
+    s = dict(system)
+    if grid is None:
+        grid = [max(_smooth_at_least(math.ceil(L / spacing)), 2 * order) for L in s["box"]]
+    s.update(elec="pme", pme_order=int(order), ewald_rtol=float(rtol),
+             pme_grid=np.asarray(grid, np.int32), name=s["name"] + "+pme")
+    return s
+
+
 def noise_sigma(system, sigma=None):
     """Per-atom Gaussian step size of a Brownian path: sqrt(2 kT dt / (m nu)) unless a
     fixed value is given (cfg1 uses 0.005 nm)."""
