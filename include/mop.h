@@ -14,14 +14,23 @@
  *     Hessian term of eq. (5) replaced by the exact Hessian-vector product, or, for
  *     comparison, computed as in eq. (5).
  *
- * The potential is the short-range part of a molecular force field: Lennard-Jones
- * (Lorentz-Berthelot mixing) plus reaction-field electrostatics, both shifted-force at
- * r_cut, harmonic bonds, and exclusion of 1-2/1-3 bonded pairs; orthorhombic periodic
- * box with r_cut < min(box)/2.  Units: nm, ps, amu, kJ/mol, e.
+ * The potential is a molecular force field: Lennard-Jones (Lorentz-Berthelot mixing)
+ * plus reaction-field electrostatics, both shifted-force at r_cut, harmonic bonds, and
+ * exclusion of 1-2/1-3 bonded pairs; orthorhombic periodic box with
+ * r_cut < min(box)/2.  Units: nm, ps, amu, kJ/mol, e.  Alternatively (elec =
+ * MOP_ELEC_PME) electrostatics is particle-mesh Ewald, the method of the paper's
+ * standard MD runs (Appendix A.1): the Ewald real-space term f q_i q_j erfc(beta r)/r,
+ * shifted-force at r_cut, with beta from erfc(beta r_cut) = ewald_rtol; excluded pairs
+ * within r_cut carry -f q_i q_j erf(beta r)/r; the reciprocal part is smooth PME
+ * (Essmann et al. 1995) with B-spline order pme_order on a pme_grid grid; plus the
+ * self term -f beta/sqrt(pi) sum q^2 and the neutralising background
+ * -f pi (sum q)^2 / (2 V beta^2).  Forces and the Hessian-vector product of every term
+ * are exact derivatives of that energy.
  *
  * Precision: pair forces and pair Hessian-vector products are evaluated in FP32 from
- * 32-bit fixed-point coordinates (exact minimum image); bonds, residuals, energies and
- * the gradient assembly are FP64.
+ * 32-bit fixed-point coordinates (exact minimum image); bonds, residuals, energies,
+ * the PME reciprocal part (spline weights, grids, FFTs) and the gradient assembly are
+ * FP64.
  *
  * Conventions for every compute call:
  *   - Array arguments are DEVICE pointers to C-contiguous arrays, bead-major:
@@ -78,7 +87,17 @@ typedef struct mop_bias_s* mop_bias;
  *                   NULL: derived from the bonds, which must then form linear chains.
  *   r_cut (nm), eps_rf, eps_r (reaction field: k_rf = (eps_rf - eps_r) /
  *                   ((2 eps_rf + eps_r) r_cut^3)), dt (ps), nu (1/ps)
+ *   elec            MOP_ELEC_RF (0, reaction field) or MOP_ELEC_PME (1, particle-mesh
+ *                   Ewald; eps_rf is then unused and eps_r divides f as before)
+ *   pme_order       B-spline order 4, 6 or 8 (0: 4)
+ *   ewald_rtol      erfc(beta r_cut) (0: 1e-5)
+ *   pme_grid[3]     grid points per axis, each >= pme_order, product <= 2^27 (0 for all
+ *                   three: the smallest sizes with prime factors 2, 3, 5, 7 that are at
+ *                   least L/0.12 nm and at least 2 pme_order)
+ * PME systems take plans without MOP_PLAN_NEWTON3 and are not accepted by mop_batch.
  */
+#define MOP_ELEC_RF 0
+#define MOP_ELEC_PME 1
 typedef struct {
     int32_t Q;
     double box[3];
@@ -95,6 +114,10 @@ typedef struct {
     const int32_t* excl_mol;
     const int32_t* excl_pos;
     double r_cut, eps_rf, eps_r, dt, nu;
+    int32_t elec;
+    int32_t pme_order;
+    double ewald_rtol;
+    int32_t pme_grid[3];
 } mop_system_desc;
 
 /*
@@ -139,8 +162,14 @@ void mop_ctx_destroy(mop_ctx ctx);
 int mop_system_create(mop_ctx ctx, const mop_system_desc* desc, mop_system* out);
 void mop_system_destroy(mop_system sys);
 
+/* PME parameters a system was created with: grid points per axis and beta (nm^-1).
+ * MOP_EINVAL for a reaction-field system. */
+int mop_system_pme_info(mop_system sys, int32_t grid[3], double* beta);
+
 /* Plan for paths of up to `max_beads` beads of one system (also the maximum B of
- * bead_forces / bead_hvp).  opts may be NULL.  Allocates device memory. */
+ * bead_forces / bead_hvp).  opts may be NULL.  Allocates device memory; for a PME
+ * system also creates the batched rocFFT plans (max_beads grids per transform).
+ * MOP_EINVAL for MOP_PLAN_NEWTON3 with a PME system. */
 int mop_plan_create(mop_system sys, int32_t max_beads, const mop_plan_opts* opts, mop_plan* out);
 void mop_plan_destroy(mop_plan plan);
 
@@ -263,7 +292,8 @@ int pmd_step(mop_plan plan, mop_bias bias, double* R, double* V, double* G, int3
  * Batch of P independent paths (each with its own plan/system and bead count),
  * evaluated together: every phase of all paths is one kernel launch.  Paths are packed
  * back to back in one buffer: path p occupies N_p*Q_p*3 doubles starting at element
- * sum_{q<p} N_q*Q_q*3 of R (and of G).
+ * sum_{q<p} N_q*Q_q*3 of R (and of G).  Reaction-field systems only (MOP_EINVAL for a
+ * plan of a PME system).
  */
 int mop_batch_create(int32_t P, const mop_plan* plans, const int32_t* N, mop_batch* out);
 void mop_batch_destroy(mop_batch batch);

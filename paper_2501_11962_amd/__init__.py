@@ -25,6 +25,7 @@ MOP_OK = 0
 MOP_DEV_NONFINITE = 1
 MOP_DEV_CAPACITY = 2
 MOP_PLAN_NEWTON3 = 1
+MOP_ELEC_RF, MOP_ELEC_PME = 0, 1
 
 _lib = None
 
@@ -45,6 +46,8 @@ class _Desc(C.Structure):
         ("bond_k", C.c_void_p), ("excl_mol", C.c_void_p), ("excl_pos", C.c_void_p),
         ("r_cut", C.c_double), ("eps_rf", C.c_double), ("eps_r", C.c_double),
         ("dt", C.c_double), ("nu", C.c_double),
+        ("elec", C.c_int32), ("pme_order", C.c_int32), ("ewald_rtol", C.c_double),
+        ("pme_grid", C.c_int32 * 3),
     ]
 
 
@@ -72,7 +75,7 @@ EXPORTS = [
     "mop_batch_create", "mop_batch_destroy", "mop_batch_workspace_size",
     "mop_batch_veff_grad", "mop_status", "mop_status_clear", "mop_strerror", "mop_plan_info",
     "veff_grad_timed", "pmd_step", "mop_bias_create", "mop_bias_destroy", "mop_bias_reset",
-    "mop_bias_apply", "mop_bias_history",
+    "mop_bias_apply", "mop_bias_history", "mop_system_pme_info",
 ]
 PHASES = ["bin", "force", "resid", "hvp", "fd", "assemble"]
 
@@ -116,6 +119,7 @@ def lib():
         "mop_bias_reset": ([vp], C.c_int),
         "mop_bias_apply": ([vp, vp, i32, vp, vp, i32, vp], C.c_int),
         "mop_bias_history": ([vp, C.POINTER(i32), vp, vp, i32], C.c_int),
+        "mop_system_pme_info": ([vp, C.POINTER(i32), C.POINTER(C.c_double)], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -182,6 +186,15 @@ class _HostArrays:
         d.excl_pos = self.pos.ctypes.data if use_molecules else None
         d.r_cut, d.eps_rf = float(s["rc"]), float(s["eps_rf"])
         d.eps_r, d.dt, d.nu = float(s.get("eps_r", 1.0)), float(s["dt"]), float(s["nu"])
+        elec = s.get("elec", "rf")
+        if elec not in ("rf", "pme"):
+            raise ValueError("elec must be 'rf' or 'pme'")
+        d.elec = MOP_ELEC_PME if elec == "pme" else MOP_ELEC_RF
+        if elec == "pme":
+            d.pme_order = int(s.get("pme_order", 0))
+            d.ewald_rtol = float(s.get("ewald_rtol", 0.0))
+            g = s.get("pme_grid")
+            d.pme_grid[:] = [0, 0, 0] if g is None else [int(k) for k in g]
         self.desc = d
 
 
@@ -221,6 +234,13 @@ class System:
         _check(lib().mop_system_create(ctx.h, C.byref(self._host.desc), C.byref(h)),
                "mop_system_create")
         self.h = h
+
+    def pme_info(self):
+        """(grid (3,), beta) of a PME system."""
+        g = (C.c_int32 * 3)()
+        b = C.c_double()
+        _check(lib().mop_system_pme_info(self.h, g, C.byref(b)), "mop_system_pme_info")
+        return [int(v) for v in g], float(b.value)
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:

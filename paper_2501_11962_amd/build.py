@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmop.so")
 SOURCES = ["kernels_bin.hip", "kernels_pair.hip", "kernels_path.hip", "kernels_pmd.hip", "kernels_bias.hip",
-           "mop_api.hip"]
+           "kernels_pme.hip", "mop_api.hip"]
 ARCH = os.environ.get("MOP_OFFLOAD_ARCH", "gfx950")
 
 # Packed FP32 instructions are switched off (the compiler may otherwise form
@@ -55,7 +55,7 @@ def build(verbose=False, jobs=None):
     if failed:
         raise RuntimeError(f"hipcc failed for {failed}")
     tmp = LIB + f".tmp{os.getpid()}"
-    cmd = [cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
+    cmd = [cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp, "-lrocfft"]
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
     return LIB

@@ -37,6 +37,13 @@
 //       where b12 r^-6 + b6 = -8 (0.75 a12 r^-6 + G6) (b12 = -14 a12, b6 = -8 a6), so
 //       the Hessian kernel reads one table entry {a12, a6, csf, 0.75 a12} per pair
 //   F_i += g d,   (H v)_i += g (v_i - v_j) + h (d . (v_i - v_j)) d   (j: the opposite)
+//
+// Ewald variant (EL = 1, systems with particle-mesh Ewald): the reaction-field terms
+// become the Ewald real-space term qq psi(r), psi = erfc(beta r)/r, shifted-force at r_c
+// (C1 = csf + qq crf1 with crf1 = -psi'(r_c)), and excluded partners within r_c carry
+// the correction qq (erfc(beta r) - 1)/r = -qq erf(beta r)/r instead of nothing.  With
+// E = erfc(beta r) (minus 1 for excluded pairs) and D = 2 beta/sqrt(pi) exp(-beta^2 r^2):
+//   g_el = -(D r^-2 + E r^-3),   h_el = (2 beta^2 D + 3 D r^-2 + 3 E r^-3) r^-2.
 #include <algorithm>
 
 #include "device_common.h"
@@ -67,7 +74,7 @@ struct IAtom {
 };
 
 struct PairK {
-    float sx, sy, sz, rc2, krf2, crf1, krf, crf, e0rf;
+    float sx, sy, sz, rc2, krf2, crf1, krf, crf, e0rf, beta, c2b, b2x2;
 };
 
 // One pair term for lane atom I and j-atom (jx, jy, jz): coordinates relative to the
@@ -75,7 +82,7 @@ struct PairK {
 // HVP: g (v_i - v_j) + h (d . (v_i - v_j)) d) is added to (ax, ay, az) with fused
 // multiply-adds; with T_OUT it is also returned in t (for the j side).  tabrow points
 // at the type-table row of atom i.
-template <int MODE, bool EX, bool WANTE, bool T_OUT>
+template <int MODE, bool EX, bool WANTE, bool T_OUT, int EL>
 __device__ __forceinline__ void pair_term(const IAtom& I, const PairK& P, const float4* tabrow,
                                           int ntab,
                                           float jx, float jy, float jz,
@@ -94,7 +101,11 @@ __device__ __forceinline__ void pair_term(const IAtom& I, const PairK& P, const 
         dz = jz - I.z;
     }
     const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-    const bool in = valid & I.v & (r2 < P.rc2) & ((unsigned)(I.key2 - kj) > 4u);
+    // same molecule within two chain positions (the atom itself: I.key2 - kj == 2)
+    const bool exc = (unsigned)(I.key2 - kj) <= 4u;
+    const bool near = valid & I.v & (r2 < P.rc2);
+    const bool in = near & !exc;
+    const bool cor = EL == 1 && near && exc && (I.key2 - kj != 2);  // Ewald correction
     // masked lanes (self pair at r = 0, stale ring entries) may form inf/NaN here; every
     // result they feed is replaced by 0 through a select below, never multiplied
     const float r2s = r2;
@@ -107,10 +118,22 @@ __device__ __forceinline__ void pair_term(const IAtom& I, const PairK& P, const 
     const float C1 = fmaf(qq, P.crf1, T.z);
     const float G6 = fmaf(T.x, rinv6, T.y);
     const float rinv8 = rinv6 * rinv2;
-    float g = G6 * rinv8;
-    g = fmaf(qq, P.krf2 - rinv3, g);
-    g = fmaf(C1, rinv, g);
-    g = in ? g : 0.0f;
+    float g, E = 0.0f, D = 0.0f, r = 0.0f;
+    if (EL == 0) {
+        g = G6 * rinv8;
+        g = fmaf(qq, P.krf2 - rinv3, g);
+        g = fmaf(C1, rinv, g);
+        g = in ? g : 0.0f;
+    } else {
+        r = r2s * rinv;
+        const float bx = P.beta * r;
+        const float ec = erfcf(bx);
+        D = P.c2b * __expf(-bx * bx);
+        E = exc ? ec - 1.0f : ec;
+        const float ge = -fmaf(D, rinv2, E * rinv3);
+        const float gs = fmaf(G6, rinv8, C1 * rinv);
+        g = in ? fmaf(qq, ge, gs) : (cor ? qq * ge : 0.0f);
+    }
     if (MODE == 0) {
         if (T_OUT) {
             tx = g * dx;
@@ -126,19 +149,26 @@ __device__ __forceinline__ void pair_term(const IAtom& I, const PairK& P, const 
         }
         if (WANTE) {
             const float4 T2 = tabrow[ntab + tj];
-            const float r = r2s * rinv;
+            if (EL == 0) r = r2s * rinv;
             float e = fmaf(T2.z, rinv6, -T2.w) * rinv6;
-            const float erf = rinv + P.krf * r2s - P.crf + P.e0rf + P.crf1 * r;
-            e = fmaf(qq, erf, e);
+            const float eel = EL == 0 ? rinv + P.krf * r2s - P.crf + P.e0rf + P.crf1 * r
+                                      : fmaf(E, rinv, fmaf(P.crf1, r, P.e0rf));
+            e = fmaf(qq, eel, e);
             e += fmaf(T.z, r, T.w);
-            en = in ? e : 0.0f;
+            en = in ? e : (cor ? qq * E * rinv : 0.0f);
         }
     } else {
         const float h6 = fmaf(T.w, rinv6, G6);
         float h = h6 * (rinv8 * (-8.0f * rinv2));
-        h = fmaf(3.0f * qq, rinv3 * rinv2, h);
-        h = fmaf(-C1, rinv3, h);
-        h = in ? h : 0.0f;
+        if (EL == 0) {
+            h = fmaf(3.0f * qq, rinv3 * rinv2, h);
+            h = fmaf(-C1, rinv3, h);
+            h = in ? h : 0.0f;
+        } else {
+            const float he = fmaf(P.b2x2, D, 3.0f * fmaf(D, rinv2, E * rinv3)) * rinv2;
+            h = fmaf(-C1, rinv3, h);
+            h = in ? fmaf(qq, he, h) : (cor ? qq * he : 0.0f);
+        }
         const float dvx = I.vx - vjx, dvy = I.vy - vjy, dvz = I.vz - vjz;
         const float sd = fmaf(dx, dvx, fmaf(dy, dvy, dz * dvz));
         const float hs = h * sd;
@@ -157,7 +187,7 @@ __device__ __forceinline__ void pair_term(const IAtom& I, const PairK& P, const 
     }
 }
 
-template <int MODE, int PW, int N3>
+template <int MODE, int PW, int N3, int EL>
 __global__ void __launch_bounds__(64 * PW) k_pair(const SegDev* __restrict__ segs, Launch L,
                                                  char* __restrict__ ws, int outsel, int energy_bead,
                                                  int lists) {
@@ -217,6 +247,9 @@ __global__ void __launch_bounds__(64 * PW) k_pair(const SegDev* __restrict__ seg
     P.krf = sg->s.krf;
     P.crf = sg->s.crf;
     P.e0rf = sg->s.e0rf;
+    P.beta = sg->s.ew_beta;
+    P.c2b = sg->s.ew_c2b;
+    P.b2x2 = sg->s.ew_b2x2;
     const float sx = P.sx, sy = P.sy, sz = P.sz;
     const float rcs = sg->s.rcs, rcs2 = sg->s.rcs2;
 
@@ -374,17 +407,17 @@ __global__ void __launch_bounds__(64 * PW) k_pair(const SegDev* __restrict__ seg
         const float qj = __uint_as_float(uj.w);
         if (exact) {
             if (wantE)
-                pair_term<MODE, true, true, false>(I, P, tabrow, ntab, jx, jy, jz, qj, mj.x, mj.y, vjx,
+                pair_term<MODE, true, true, false, EL>(I, P, tabrow, ntab, jx, jy, jz, qj, mj.x, mj.y, vjx,
                                             vjy, vjz, vj, ax, ay, az, tx, ty, tz, en);
             else
-                pair_term<MODE, true, false, false>(I, P, tabrow, ntab, jx, jy, jz, qj, mj.x, mj.y, vjx,
+                pair_term<MODE, true, false, false, EL>(I, P, tabrow, ntab, jx, jy, jz, qj, mj.x, mj.y, vjx,
                                              vjy, vjz, vj, ax, ay, az, tx, ty, tz, en);
         } else {
             if (wantE)
-                pair_term<MODE, false, true, false>(I, P, tabrow, ntab, jx, jy, jz, qj, mj.x, mj.y, vjx,
+                pair_term<MODE, false, true, false, EL>(I, P, tabrow, ntab, jx, jy, jz, qj, mj.x, mj.y, vjx,
                                              vjy, vjz, vj, ax, ay, az, tx, ty, tz, en);
             else
-                pair_term<MODE, false, false, false>(I, P, tabrow, ntab, jx, jy, jz, qj, mj.x, mj.y, vjx,
+                pair_term<MODE, false, false, false, EL>(I, P, tabrow, ntab, jx, jy, jz, qj, mj.x, mj.y, vjx,
                                               vjy, vjz, vj, ax, ay, az, tx, ty, tz, en);
         }
         eacc += 0.5f * en;
@@ -429,7 +462,7 @@ __global__ void __launch_bounds__(64 * PW) k_pair(const SegDev* __restrict__ seg
                 }
             }
             float tx, ty, tz, en = 0.f;
-            pair_term<MODE, EX, WE, N3 == 1>(I, P, tabrow, ntab, jxv, jyv, jzv, qjv, kj, tjv, vjx, vjy,
+            pair_term<MODE, EX, WE, N3 == 1, EL>(I, P, tabrow, ntab, jxv, jyv, jzv, qjv, kj, tjv, vjx, vjy,
                                              vjz, valid, ax, ay, az, tx, ty, tz, en);
             if (WE) eacc += N3 ? en : 0.5f * en;
             if (N3) {
@@ -730,7 +763,7 @@ __global__ void __launch_bounds__(EWB) k_unsort(const SegDev* __restrict__ segs,
     wsp<float4>(ws, o)[(size_t)b * Q + i] = v;
 }
 
-template <int MODE, int PW, int N3>
+template <int MODE, int PW, int N3, int EL>
 static void launch_pair_t(const SegDev* dsegs, const SegDev* hsegs, const Launch& base, char* ws,
                           int outsel, int energy_bead, int lists, hipStream_t st) {
     Launch L = base;
@@ -746,35 +779,42 @@ static void launch_pair_t(const SegDev* dsegs, const SegDev* hsegs, const Launch
     const size_t lds = TAB_COPIES<MODE> * (size_t)L.ntmax * L.ntmax * sizeof(float4) +
                        (size_t)PW * Fields<MODE, N3>::NF * RING * sizeof(float) +
                        (size_t)PW * CLIST * sizeof(int);
-    hipLaunchKernelGGL((k_pair<MODE, PW, N3>), dim3(grid), dim3(64 * PW), lds, st, dsegs, L, ws,
+    hipLaunchKernelGGL((k_pair<MODE, PW, N3, EL>), dim3(grid), dim3(64 * PW), lds, st, dsegs, L, ws,
                        outsel, energy_bead, lists);
 }
 
-template <int MODE, int N3>
+template <int MODE, int N3, int EL>
 static void launch_pair_w(const SegDev* dsegs, const SegDev* hsegs, const Launch& base, char* ws,
                           int outsel, int energy_bead, int waves, int lists, hipStream_t st) {
     switch (waves) {
-        case 1: launch_pair_t<MODE, 1, N3>(dsegs, hsegs, base, ws, outsel, energy_bead, lists, st); break;
-        case 2: launch_pair_t<MODE, 2, N3>(dsegs, hsegs, base, ws, outsel, energy_bead, lists, st); break;
-        case 8: launch_pair_t<MODE, 8, N3>(dsegs, hsegs, base, ws, outsel, energy_bead, lists, st); break;
-        default: launch_pair_t<MODE, 4, N3>(dsegs, hsegs, base, ws, outsel, energy_bead, lists, st); break;
+        case 1: launch_pair_t<MODE, 1, N3, EL>(dsegs, hsegs, base, ws, outsel, energy_bead, lists, st); break;
+        case 2: launch_pair_t<MODE, 2, N3, EL>(dsegs, hsegs, base, ws, outsel, energy_bead, lists, st); break;
+        case 8: launch_pair_t<MODE, 8, N3, EL>(dsegs, hsegs, base, ws, outsel, energy_bead, lists, st); break;
+        default: launch_pair_t<MODE, 4, N3, EL>(dsegs, hsegs, base, ws, outsel, energy_bead, lists, st); break;
     }
 }
 
 void run_pair(const SegDev* dsegs, const SegDev* hsegs, const Launch& base, char* ws, int mode,
               int outsel, int energy_bead, int waves, int newton3, hipStream_t st, int lists) {
     if (mode == 1) outsel = 1;
+    // Ewald systems: full-shell kernels only (the host rejects Newton-3 plans for them;
+    // a launch holds one path then)
+    if (hsegs[0].s.elec == 1) {
+        if (mode == 0) launch_pair_w<0, 0, 1>(dsegs, hsegs, base, ws, outsel, energy_bead, waves, lists, st);
+        else launch_pair_w<1, 0, 1>(dsegs, hsegs, base, ws, outsel, energy_bead, waves, lists, st);
+        return;
+    }
     if (newton3) {
-        if (mode == 0) launch_pair_w<0, 1>(dsegs, hsegs, base, ws, outsel, energy_bead, waves, 0, st);
-        else launch_pair_w<1, 1>(dsegs, hsegs, base, ws, outsel, energy_bead, waves, 0, st);
+        if (mode == 0) launch_pair_w<0, 1, 0>(dsegs, hsegs, base, ws, outsel, energy_bead, waves, 0, st);
+        else launch_pair_w<1, 1, 0>(dsegs, hsegs, base, ws, outsel, energy_bead, waves, 0, st);
         Launch L = base;
         L.pf[0] = 0;
         for (int p = 0; p < base.nseg; ++p) L.pf[p + 1] = L.pf[p] + base.nb[p] * hsegs[p].bpb;
         if (L.pf[base.nseg] > 0)
             hipLaunchKernelGGL(k_unsort, dim3(L.pf[base.nseg]), dim3(EWB), 0, st, dsegs, L, ws, outsel);
     } else {
-        if (mode == 0) launch_pair_w<0, 0>(dsegs, hsegs, base, ws, outsel, energy_bead, waves, lists, st);
-        else launch_pair_w<1, 0>(dsegs, hsegs, base, ws, outsel, energy_bead, waves, lists, st);
+        if (mode == 0) launch_pair_w<0, 0, 0>(dsegs, hsegs, base, ws, outsel, energy_bead, waves, lists, st);
+        else launch_pair_w<1, 0, 0>(dsegs, hsegs, base, ws, outsel, energy_bead, waves, lists, st);
     }
 }
 

@@ -147,6 +147,16 @@ __device__ double pair_energy_of_bead(const SegDev& sg, char* ws, int b, int t0,
     return e0 + e1;
 }
 
+// This thread's share of the PME reciprocal energy of bead b (partials of the solve
+// kernel, already halved); 0 without PME.
+__device__ double pme_energy_of_bead(const SegDev& sg, char* ws, int b, int t0, int stride) {
+    if (sg.s.elec != 1) return 0.0;
+    const double* ep = wsp<const double>(ws, sg.o_pep) + (size_t)b * sg.s.nsb;
+    double e = 0.0;
+    for (int k = t0; k < sg.s.nsb; k += stride) e += ep[k];
+    return e;
+}
+
 // Block-wide sum over RVB threads (result valid in thread 0).
 constexpr int RVB = 1024;
 __device__ __forceinline__ double block_sum_rvb(double v, double* sh) {
@@ -175,9 +185,10 @@ __global__ void __launch_bounds__(RVB) k_reduce_veff(const SegDev* __restrict__ 
     double es = 0.0, eb = 0.0;
     for (int k = threadIdx.x; k < nbr * sg.bpb; k += RVB) es += rp[2 * k];
     for (int k = threadIdx.x; k < sg.bpb; k += RVB) eb += rp[2 * k + 1];
-    const double ep = pair_energy_of_bead(sg, ws, 0, threadIdx.x, RVB);
+    const double ep = pair_energy_of_bead(sg, ws, 0, threadIdx.x, RVB) +
+                      pme_energy_of_bead(sg, ws, 0, threadIdx.x, RVB);
     const double S_es = block_sum_rvb(es, sh);
-    const double S_u = block_sum_rvb(eb + ep, sh);
+    const double S_u = block_sum_rvb(eb + ep, sh) + (sg.s.elec == 1 ? sg.s.e_const : 0.0);
     if (threadIdx.x == 0) {
         double* er = wsp<double>(ws, sg.o_eres);
         er[0] = S_u + S_es;
@@ -228,9 +239,10 @@ __global__ void __launch_bounds__(EWB) k_reduce_beads(const SegDev* __restrict__
     const double* rp = wsp<const double>(cp.ws, sg.o_rpart);
     double eb = 0.0;
     for (int k = threadIdx.x; k < sg.bpb; k += EWB) eb += rp[2 * ((size_t)b * sg.bpb + k) + 1];
-    const double ep = pair_energy_of_bead(sg, cp.ws, b, threadIdx.x, EWB);
+    const double ep = pair_energy_of_bead(sg, cp.ws, b, threadIdx.x, EWB) +
+                      pme_energy_of_bead(sg, cp.ws, b, threadIdx.x, EWB);
     const double s = block_sum(eb + ep, sh);
-    if (threadIdx.x == 0) cp.Uout[sg.vidx + b] = s;
+    if (threadIdx.x == 0) cp.Uout[sg.vidx + b] = s + (sg.s.elec == 1 ? sg.s.e_const : 0.0);
 }
 
 // bead_hvp: vector in slot order, FP32.

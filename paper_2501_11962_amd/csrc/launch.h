@@ -49,4 +49,20 @@ void run_pmd_post(const SegDev* dsegs, const SegDev* hsegs, const Launch& base, 
                   const double* G, const PmdCoef& pc, char* ws, double* energies, int stride,
                   int has_bias, hipStream_t st);
 
+// Particle-mesh Ewald (single-path launches; nb pair beads).  kind 0: charges / forces,
+// kind 1: dipoles q v / Hessian-vector product.  fdsign != 0 displaces R by fdsign * eps d
+// (finite-difference term).  Spreading clears the fixed-point grid first.
+void run_pme_spread(const SegDev* dsegs, const SegDev& h, int nb, char* ws, const double* R,
+                    const double* V, int kind, int fdsign, double fdh, hipStream_t st);
+void run_pme_convert(const SegDev* dsegs, const SegDev& h, int nb, int nbatch, char* ws, int kind,
+                     hipStream_t st);
+void run_pme_solve(const SegDev* dsegs, const SegDev& h, int nb, char* ws, int want_e,
+                   hipStream_t st);
+// outsel: 0 f32, 1 hv32, 2 f32m; use_pgr: kind-0 potential read from pgr instead of pphi.
+void run_pme_gather(const SegDev* dsegs, const SegDev& h, int nb, char* ws, const double* R,
+                    const double* V, int kind, int fdsign, double fdh, int outsel, int use_pgr,
+                    hipStream_t st);
+void run_pme_vmax(const SegDev* dsegs, const SegDev& h, int nb, char* ws, const double* V,
+                  hipStream_t st);
+
 }  // namespace mop

@@ -1,6 +1,7 @@
 // Host runtime behind include/mop.h: validation, device tables, plan geometry,
 // workspace layout and the call sequences of every entry point.
 #include <hip/hip_runtime.h>
+#include <rocfft/rocfft.h>
 
 #include <algorithm>
 #include <cmath>
@@ -19,8 +20,22 @@ namespace {
 
 constexpr double F_ELEC = 138.935458;  // kJ mol^-1 nm e^-2
 constexpr double SEARCH_MARGIN = 1.0e-4;  // nm added to the cutoff for neighbour pruning
+constexpr double PI = 3.14159265358979323846;
+constexpr double PME_SPACING = 0.12;      // nm per grid point of the automatic PME grid
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+template <class T>
+T* wsp_host(char* ws, size_t off) {
+    return reinterpret_cast<T*>(ws + off);
+}
+
+// Batched double-precision 3-D real FFTs of one PME grid shape (rocFFT).
+struct PmeFft {
+    rocfft_plan fwd = nullptr, bwd = nullptr;
+    rocfft_execution_info info = nullptr;
+    size_t work = 0;
+};
 
 }  // namespace
 
@@ -34,6 +49,7 @@ struct mop_system_s {
     SysDev dev;           // device pointers; geometry fields filled per plan
     double box[3];
     double rc;
+    double beta;          // PME systems
     std::vector<void*> allocs;
 };
 
@@ -45,6 +61,7 @@ struct mop_plan_s {
     SegDev hseg;          // single-path layout (capacity max_beads)
     SegDev* dseg;
     size_t ws_bytes;
+    PmeFft fft;           // PME systems
 };
 
 struct mop_bias_s {
@@ -97,7 +114,68 @@ static int check_desc(const mop_system_desc* d) {
     if (d->excl_mol)
         for (int i = 0; i < d->Q; ++i)
             if (d->excl_mol[i] < 0 || d->excl_pos[i] < 0) return MOP_EINVAL;
+    if (d->elec != MOP_ELEC_RF && d->elec != MOP_ELEC_PME) return MOP_EINVAL;
+    if (d->elec == MOP_ELEC_PME) {
+        const int p = d->pme_order ? d->pme_order : 4;
+        if (p != 4 && p != 6 && p != 8) return MOP_EINVAL;
+        if (!(d->ewald_rtol >= 0.0 && d->ewald_rtol < 1.0)) return MOP_EINVAL;
+        const int* g = d->pme_grid;
+        const bool autog = g[0] == 0 && g[1] == 0 && g[2] == 0;
+        if (!autog) {
+            double n = 1.0;
+            for (int a = 0; a < 3; ++a) {
+                if (g[a] < p) return MOP_EINVAL;
+                n *= g[a];
+            }
+            if (n > 134217728.0) return MOP_EINVAL;
+        }
+    }
     return MOP_OK;
+}
+
+// ---------------------------------------------------------------------------------
+// particle-mesh Ewald constants
+// ---------------------------------------------------------------------------------
+
+// Cardinal B-spline M_n(x) by its recursion from M_2 (host, for the spline moduli).
+static double bspline_host(int n, double x) {
+    if (n == 2) return (x >= 0.0 && x <= 2.0) ? 1.0 - std::fabs(x - 1.0) : 0.0;
+    return (x * bspline_host(n - 1, x) + (n - x) * bspline_host(n - 1, x - 1.0)) / (n - 1);
+}
+
+// |b(m)|^2 = 1 / |sum_{k=0}^{p-2} M_p(k+1) exp(2 pi i m k / K)|^2, m = 0..K-1.
+static std::vector<double> bspline_moduli_host(int p, int K) {
+    std::vector<double> out(K);
+    for (int m = 0; m < K; ++m) {
+        double re = 0.0, im = 0.0;
+        for (int k = 0; k <= p - 2; ++k) {
+            const double w = bspline_host(p, k + 1.0), a = 2.0 * PI * m * k / K;
+            re += w * std::cos(a);
+            im += w * std::sin(a);
+        }
+        out[m] = 1.0 / (re * re + im * im);
+    }
+    return out;
+}
+
+static int smooth_at_least(int n) {
+    for (int k = std::max(n, 1);; ++k) {
+        int m = k;
+        for (int f : {2, 3, 5, 7})
+            while (m % f == 0) m /= f;
+        if (m == 1) return k;
+    }
+}
+
+// beta with erfc(beta r_c) = rtol (bisection).
+static double ewald_beta(double rc, double rtol) {
+    double lo = 0.0, hi = 1.0;
+    while (std::erfc(hi * rc) > rtol) hi *= 2.0;
+    for (int it = 0; it < 200; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        (std::erfc(mid * rc) > rtol ? lo : hi) = mid;
+    }
+    return 0.5 * (lo + hi);
 }
 
 // Exclusion key per atom: molecule id * 2^sh + position along the chain, with
@@ -204,6 +282,16 @@ static size_t layout(SegDev& sg, int maxb, int maxN, size_t base) {
     if (s.lcap > 0) {
         take(sg.o_nl, B * s.cpb * (size_t)s.lcap * 4);
         take(sg.o_nlc, B * s.cpb * 4);
+    }
+    sg.o_pgi = sg.o_pgr = sg.o_pgc = sg.o_pphi = sg.o_pep = sg.o_pfw = 0;
+    if (s.elec == 1) {
+        const size_t Kt = (size_t)s.Kg[0] * s.Kg[1] * s.Kg[2];
+        const size_t Kc = (size_t)s.Kg[0] * s.Kg[1] * s.Kzh;
+        take(sg.o_pgi, B * Kt * 8);
+        take(sg.o_pgr, B * Kt * 8);
+        take(sg.o_pgc, B * Kc * 16);
+        take(sg.o_pphi, B * Kt * 8);
+        take(sg.o_pep, B * (size_t)s.nsb * 8);
     }
     sg.maxb = maxb;
     sg.maxN = maxN;
@@ -345,6 +433,65 @@ int mop_system_create(mop_ctx ctx, const mop_system_desc* d, mop_system* out) {
     s.crf = (float)crf;
     s.crf1 = (float)crf1;
     s.e0rf = (float)(-rc * crf1);
+    s.elec = d->elec;
+    std::vector<double> phihat;
+    if (d->elec == MOP_ELEC_PME) {
+        // Ewald real space: psi = erfc(beta r)/r, shifted-force at r_c
+        const double rtol = d->ewald_rtol > 0.0 ? d->ewald_rtol : 1e-5;
+        const double beta = ewald_beta(rc, rtol);
+        sys->beta = beta;
+        const double c2b = 2.0 * beta / std::sqrt(PI);
+        const double psic = std::erfc(beta * rc) / rc;
+        const double dpsic = -std::erfc(beta * rc) / (rc * rc) - c2b * std::exp(-beta * beta * rc * rc) / rc;
+        s.krf = s.krf2 = s.crf = 0.0f;
+        s.crf1 = (float)(-dpsic);
+        s.e0rf = (float)(-psic + rc * dpsic);
+        s.ew_beta = (float)beta;
+        s.ew_c2b = (float)c2b;
+        s.ew_b2x2 = (float)(2.0 * beta * beta);
+        // reciprocal part
+        const int p = d->pme_order ? d->pme_order : 4;
+        s.pme_p = p;
+        const bool autog = d->pme_grid[0] == 0 && d->pme_grid[1] == 0 && d->pme_grid[2] == 0;
+        for (int a = 0; a < 3; ++a)
+            s.Kg[a] = autog ? std::max(smooth_at_least((int)std::ceil(d->box[a] / PME_SPACING)), 2 * p)
+                            : d->pme_grid[a];
+        s.Kzh = s.Kg[2] / 2 + 1;
+        const size_t Kc = (size_t)s.Kg[0] * s.Kg[1] * s.Kzh;
+        s.nsb = (int)((Kc + PME_BLOCK - 1) / PME_BLOCK);
+        double klmax = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            s.kl[a] = s.Kg[a] / d->box[a];
+            klmax = std::max(klmax, s.kl[a]);
+        }
+        double sabs = 0.0, sq = 0.0, sq2 = 0.0;
+        for (int i = 0; i < Q; ++i) {
+            sabs += std::fabs(d->charge[i]);
+            sq += d->charge[i];
+            sq2 += d->charge[i] * d->charge[i];
+        }
+        s.qscale = sabs > 0.0 ? std::ldexp(1.0, 61 - (std::ilogb(sabs) + 1)) : 1.0;
+        s.vbound = sabs * 3.0 * klmax;
+        const double V = d->box[0] * d->box[1] * d->box[2];
+        s.e_const = -fq * beta / std::sqrt(PI) * sq2 - fq * PI * sq * sq / (2.0 * V * beta * beta);
+        // f B(m) C(m) on the half spectrum (z frequencies 0 .. Kz/2)
+        std::vector<double> bm[3];
+        for (int a = 0; a < 3; ++a) bm[a] = bspline_moduli_host(p, s.Kg[a]);
+        phihat.resize(Kc);
+        for (int mx = 0; mx < s.Kg[0]; ++mx)
+            for (int my = 0; my < s.Kg[1]; ++my)
+                for (int mz = 0; mz < s.Kzh; ++mz) {
+                    const int fx = 2 * mx < s.Kg[0] ? mx : mx - s.Kg[0];
+                    const int fy = 2 * my < s.Kg[1] ? my : my - s.Kg[1];
+                    const double ax = fx / d->box[0], ay = fy / d->box[1], az = mz / d->box[2];
+                    const double m2 = ax * ax + ay * ay + az * az;
+                    double v = 0.0;
+                    if (m2 > 0.0)
+                        v = fq * bm[0][mx] * bm[1][my] * bm[2][mz] *
+                            std::exp(-PI * PI * m2 / (beta * beta)) / (PI * V * m2);
+                    phihat[((size_t)mx * s.Kg[1] + my) * s.Kzh + mz] = v;
+                }
+    }
     // per atom
     std::vector<float> qs(Q);
     std::vector<int> typ(Q);
@@ -412,6 +559,8 @@ int mop_system_create(mop_ctx ctx, const mop_system_desc* d, mop_system* out) {
     if (!e) e = upload(sys, tab.data(), tab.size(), &s.tab);
     if (!e) e = upload(sys, tab2.data(), tab2.size(), &s.tab2);
     if (!e) e = upload(sys, tabh.data(), tabh.size(), &s.tabh);
+    if (!e && s.elec == 1) e = upload(sys, d->charge, Q, &s.qd);
+    if (!e && s.elec == 1) e = upload(sys, phihat.data(), phihat.size(), &s.phihat);
     if (e) {
         mop_system_destroy(sys);
         return e;
@@ -426,9 +575,68 @@ void mop_system_destroy(mop_system sys) {
     delete sys;
 }
 
+static void destroy_fft(PmeFft& f) {
+    if (f.fwd) (void)rocfft_plan_destroy(f.fwd);
+    if (f.bwd) (void)rocfft_plan_destroy(f.bwd);
+    if (f.info) (void)rocfft_execution_info_destroy(f.info);
+    f = PmeFft();
+}
+
+// Out-of-place double-precision real <-> half-complex 3-D transforms of `batch` grids
+// K0 x K1 x K2 (K2 fastest), real grids packed K apart, spectra Kc apart.
+static int make_fft(PmeFft& f, const int K[3], int batch) {
+    static bool ready = false;
+    if (!ready) {
+        if (rocfft_setup() != rocfft_status_success) return MOP_EHIP;
+        ready = true;
+    }
+    const size_t Kzh = K[2] / 2 + 1;
+    size_t len[3] = {(size_t)K[2], (size_t)K[1], (size_t)K[0]};
+    size_t rs[3] = {1, (size_t)K[2], (size_t)K[2] * K[1]};
+    size_t cs[3] = {1, Kzh, Kzh * K[1]};
+    const size_t rdist = (size_t)K[0] * K[1] * K[2], cdist = (size_t)K[0] * K[1] * Kzh;
+    rocfft_plan_description df = nullptr, db = nullptr;
+    bool ok = rocfft_plan_description_create(&df) == rocfft_status_success &&
+              rocfft_plan_description_create(&db) == rocfft_status_success;
+    ok = ok && rocfft_plan_description_set_data_layout(
+                   df, rocfft_array_type_real, rocfft_array_type_hermitian_interleaved, nullptr,
+                   nullptr, 3, rs, rdist, 3, cs, cdist) == rocfft_status_success;
+    ok = ok && rocfft_plan_description_set_data_layout(
+                   db, rocfft_array_type_hermitian_interleaved, rocfft_array_type_real, nullptr,
+                   nullptr, 3, cs, cdist, 3, rs, rdist) == rocfft_status_success;
+    ok = ok && rocfft_plan_create(&f.fwd, rocfft_placement_notinplace,
+                                  rocfft_transform_type_real_forward, rocfft_precision_double, 3,
+                                  len, batch, df) == rocfft_status_success;
+    ok = ok && rocfft_plan_create(&f.bwd, rocfft_placement_notinplace,
+                                  rocfft_transform_type_real_inverse, rocfft_precision_double, 3,
+                                  len, batch, db) == rocfft_status_success;
+    size_t w1 = 0, w2 = 0;
+    ok = ok && rocfft_plan_get_work_buffer_size(f.fwd, &w1) == rocfft_status_success &&
+         rocfft_plan_get_work_buffer_size(f.bwd, &w2) == rocfft_status_success;
+    ok = ok && rocfft_execution_info_create(&f.info) == rocfft_status_success;
+    if (df) (void)rocfft_plan_description_destroy(df);
+    if (db) (void)rocfft_plan_description_destroy(db);
+    if (!ok) {
+        destroy_fft(f);
+        return MOP_EHIP;
+    }
+    f.work = std::max(w1, w2);
+    return MOP_OK;
+}
+
+// One batched transform on `st` (the work buffer lives in the caller's workspace).
+static void run_fft(const PmeFft& f, bool forward, void* in, void* out, void* work, hipStream_t st) {
+    (void)rocfft_execution_info_set_stream(f.info, st);
+    if (f.work) (void)rocfft_execution_info_set_work_buffer(f.info, work, f.work);
+    void* ib[1] = {in};
+    void* ob[1] = {out};
+    (void)rocfft_execute(forward ? f.fwd : f.bwd, ib, ob, f.info);
+}
+
 int mop_plan_create(mop_system sys, int32_t max_beads, const mop_plan_opts* opts, mop_plan* out) {
     if (!sys || !out || max_beads < 1) return MOP_EINVAL;
     *out = nullptr;
+    if (sys->dev.elec == 1 && opts && (opts->flags & MOP_PLAN_NEWTON3)) return MOP_EINVAL;
     int waves = opts && opts->waves ? opts->waves : 4;
     if (waves != 1 && waves != 2 && waves != 4 && waves != 8) return MOP_EINVAL;
     if (opts && (opts->col_width < 0.0 || opts->zbin < 0.0)) return MOP_EINVAL;
@@ -444,12 +652,23 @@ int mop_plan_create(mop_system sys, int32_t max_beads, const mop_plan_opts* opts
     pl->hseg.vidx = 0;
     pl->ws_bytes = layout(pl->hseg, max_beads, max_beads, 256);
     pl->dseg = nullptr;
+    if (pl->hseg.s.elec == 1) {
+        const int e = make_fft(pl->fft, pl->hseg.s.Kg, pl->hseg.maxb);
+        if (e) {
+            delete pl;
+            return e;
+        }
+        pl->hseg.o_pfw = align256(pl->ws_bytes);
+        pl->ws_bytes = pl->hseg.o_pfw + std::max<size_t>(pl->fft.work, 256);
+    }
     if (hipMalloc(&pl->dseg, sizeof(SegDev)) != hipSuccess) {
+        destroy_fft(pl->fft);
         delete pl;
         return MOP_ENOMEM;
     }
     if (hipMemcpy(pl->dseg, &pl->hseg, sizeof(SegDev), hipMemcpyHostToDevice) != hipSuccess) {
         (void)hipFree(pl->dseg);
+        destroy_fft(pl->fft);
         delete pl;
         return MOP_EHIP;
     }
@@ -460,7 +679,16 @@ int mop_plan_create(mop_system sys, int32_t max_beads, const mop_plan_opts* opts
 void mop_plan_destroy(mop_plan plan) {
     if (!plan) return;
     if (plan->dseg) (void)hipFree(plan->dseg);
+    destroy_fft(plan->fft);
     delete plan;
+}
+
+int mop_system_pme_info(mop_system sys, int32_t grid[3], double* beta) {
+    if (!sys || sys->dev.elec != 1) return MOP_EINVAL;
+    if (grid)
+        for (int a = 0; a < 3; ++a) grid[a] = sys->dev.Kg[a];
+    if (beta) *beta = sys->beta;
+    return MOP_OK;
 }
 
 int mop_workspace_size(mop_plan plan, size_t* bytes) {
@@ -500,6 +728,38 @@ static int finish(mop_ctx ctx) {
     return hipGetLastError() == hipSuccess ? MOP_OK : MOP_EHIP;
 }
 
+// PME reciprocal forces of nb pair beads at R (displaced by fdsign eps d), added to the
+// float4 output outsel (when gather); the potential goes to pphi for the undisplaced
+// configuration (kept for the Hessian pass), else to pgr.  Energy partials are formed
+// for the undisplaced configuration.
+static void pme_forces(const mop_plan_s* pl, int nb, const CallPtrs& cp, int fdsign, int outsel,
+                       bool gather, hipStream_t st) {
+    const SegDev& h = pl->hseg;
+    char* ws = cp.ws;
+    run_pme_spread(pl->dseg, h, nb, ws, cp.R, nullptr, 0, fdsign, cp.fd_h, st);
+    run_pme_convert(pl->dseg, h, nb, h.maxb, ws, 0, st);
+    run_fft(pl->fft, true, ws + h.o_pgr, ws + h.o_pgc, ws + h.o_pfw, st);
+    run_pme_solve(pl->dseg, h, nb, ws, fdsign == 0 ? 1 : 0, st);
+    run_fft(pl->fft, false, ws + h.o_pgc, ws + (fdsign == 0 ? h.o_pphi : h.o_pgr), ws + h.o_pfw, st);
+    if (gather)
+        run_pme_gather(pl->dseg, h, nb, ws, cp.R, nullptr, 0, fdsign, cp.fd_h, outsel,
+                       fdsign != 0 ? 1 : 0, st);
+}
+
+// PME reciprocal H v of nb pair beads (V: [nb][Q][3]; needs pphi of the same beads and
+// the per-bead max |v|^2), added to hv32.
+static void pme_hvp(const mop_plan_s* pl, int nb, const CallPtrs& cp, const double* V,
+                    hipStream_t st) {
+    const SegDev& h = pl->hseg;
+    char* ws = cp.ws;
+    run_pme_spread(pl->dseg, h, nb, ws, cp.R, V, 1, 0, 0.0, st);
+    run_pme_convert(pl->dseg, h, nb, h.maxb, ws, 1, st);
+    run_fft(pl->fft, true, ws + h.o_pgr, ws + h.o_pgc, ws + h.o_pfw, st);
+    run_pme_solve(pl->dseg, h, nb, ws, 0, st);
+    run_fft(pl->fft, false, ws + h.o_pgc, ws + h.o_pgr, ws + h.o_pfw, st);
+    run_pme_gather(pl->dseg, h, nb, ws, cp.R, V, 1, 0, 0.0, 1, 0, st);
+}
+
 int bead_forces(mop_plan plan, const double* R, int32_t B, float* F, double* U, void* ws) {
     if (!plan || !R || !F || !ws) return MOP_EINVAL;
     if (B < 1) return MOP_EINVAL;
@@ -512,6 +772,7 @@ int bead_forces(mop_plan plan, const double* R, int32_t B, float* F, double* U, 
     const Launch L = one_path(B, B);
     run_binning(plan->dseg, &plan->hseg, L, cp.ws, R, 0, 0.0, st);
     run_pair(plan->dseg, &plan->hseg, L, cp.ws, 0, 0, U ? -2 : -1, plan->waves, plan->newton3, st);
+    if (plan->hseg.s.elec == 1) pme_forces(plan, B, cp, 0, 0, true, st);
     run_finalize_forces(plan->dseg, &plan->hseg, L, cp, st);
     return finish(plan->sys->ctx);
 }
@@ -529,15 +790,22 @@ int bead_hvp(mop_plan plan, const double* R, const double* V, int32_t B, float* 
     run_binning(plan->dseg, &plan->hseg, L, cp.ws, R, 0, 0.0, st);
     run_prep_v(plan->dseg, &plan->hseg, L, cp, st);
     run_pair(plan->dseg, &plan->hseg, L, cp.ws, 1, 0, -1, plan->waves, plan->newton3, st);
+    if (plan->hseg.s.elec == 1) {
+        pme_forces(plan, B, cp, 0, 0, false, st);
+        run_pme_vmax(plan->dseg, plan->hseg, B, cp.ws, V, st);
+        pme_hvp(plan, B, cp, V, st);
+    }
     run_finalize_hvp(plan->dseg, &plan->hseg, L, cp, st);
     return finish(plan->sys->ctx);
 }
 
 // The phases of V_eff and its gradient over every path of `base`.  ev, when given,
 // receives an event after each phase (MOP_NPHASES + 1 events, ev[0] at the start).
+// pl: the plan of a single-path call (PME steps run for PME systems), null for batches.
 static void path_sequence(const SegDev* dsegs, const SegDev* hsegs, const Launch& base,
                           const CallPtrs& cp, bool grad, int mode, int waves, int n3,
-                          hipStream_t st, hipEvent_t* ev = nullptr) {
+                          hipStream_t st, hipEvent_t* ev = nullptr, const mop_plan_s* pl = nullptr) {
+    const bool pme = pl && pl->hseg.s.elec == 1;
     auto mark = [&](int k) {
         if (ev) (void)hipEventRecord(ev[k], st);
     };
@@ -548,6 +816,7 @@ static void path_sequence(const SegDev* dsegs, const SegDev* hsegs, const Launch
     // exact gradients: the force pass records neighbour lists for the Hessian pass
     const int lists = (grad && mode == 0) ? 1 : 0;
     run_pair(dsegs, hsegs, base, cp.ws, 0, 0, 0, waves, n3, st, lists);
+    if (pme) pme_forces(pl, base.nb[0], cp, 0, 0, true, st);
     mark(2);
     run_resid(dsegs, hsegs, base, cp, st);
     mark(3);
@@ -558,13 +827,18 @@ static void path_sequence(const SegDev* dsegs, const SegDev* hsegs, const Launch
             Lh.nb[p] = base.N[p] - 1;
             any = any || Lh.nb[p] > 0;
         }
-        if (any && mode == 0) run_pair(dsegs, hsegs, Lh, cp.ws, 1, 0, -1, waves, n3, st, 2 * lists);
+        if (any && mode == 0) {
+            run_pair(dsegs, hsegs, Lh, cp.ws, 1, 0, -1, waves, n3, st, 2 * lists);
+            if (pme) pme_hvp(pl, Lh.nb[0], cp, wsp_host<double>(cp.ws, hsegs[0].o_d64), st);
+        }
         mark(4);
         if (any && mode == 1) {
             run_binning(dsegs, hsegs, Lh, cp.ws, cp.R, +1, cp.fd_h, st);
             run_pair(dsegs, hsegs, Lh, cp.ws, 0, 1, -1, waves, n3, st);
+            if (pme) pme_forces(pl, Lh.nb[0], cp, +1, 1, true, st);
             run_binning(dsegs, hsegs, Lh, cp.ws, cp.R, -1, cp.fd_h, st);
             run_pair(dsegs, hsegs, Lh, cp.ws, 0, 2, -1, waves, n3, st);
+            if (pme) pme_forces(pl, Lh.nb[0], cp, -1, 2, true, st);
         }
         mark(5);
         run_assemble(dsegs, hsegs, base, cp, mode, st);
@@ -588,7 +862,7 @@ int veff_energy(mop_plan plan, const double* R, int32_t N, double* veff, double*
     cp.espring = espring;
     const Launch L = one_path(N, N > 1 ? N - 1 : 1);
     path_sequence(plan->dseg, &plan->hseg, L, cp, false, 0, plan->waves, plan->newton3,
-                  plan->sys->ctx->stream);
+                  plan->sys->ctx->stream, nullptr, plan);
     return finish(plan->sys->ctx);
 }
 
@@ -605,7 +879,7 @@ int veff_grad(mop_plan plan, const double* R, int32_t N, double* G, double* veff
     cp.fd_h = fd_h;
     const Launch L = one_path(N, N > 1 ? N - 1 : 1);
     path_sequence(plan->dseg, &plan->hseg, L, cp, true, mode, plan->waves, plan->newton3,
-                  plan->sys->ctx->stream);
+                  plan->sys->ctx->stream, nullptr, plan);
     return finish(plan->sys->ctx);
 }
 
@@ -625,7 +899,8 @@ int veff_grad_timed(mop_plan plan, const double* R, int32_t N, double* G, double
     cp.veff = veff;
     cp.fd_h = fd_h;
     const Launch L = one_path(N, N > 1 ? N - 1 : 1);
-    path_sequence(plan->dseg, &plan->hseg, L, cp, true, mode, plan->waves, plan->newton3, st, ev);
+    path_sequence(plan->dseg, &plan->hseg, L, cp, true, mode, plan->waves, plan->newton3, st, ev,
+                  plan);
     int rc = finish(plan->sys->ctx);
     if (hipEventSynchronize(ev[MOP_NPHASES]) != hipSuccess) rc = MOP_EHIP;
     for (int k = 0; k < MOP_NPHASES; ++k) {
@@ -763,7 +1038,8 @@ int pmd_step(mop_plan plan, mop_bias bias, double* R, double* V, double* G, int3
         double* ek = energies ? energies + 4 * (size_t)k : nullptr;
         run_pmd_pre(plan->dseg, &plan->hseg, L, R, V, G, pc, step, st);
         cp.veff = nullptr;
-        path_sequence(plan->dseg, &plan->hseg, L, cp, true, 0, plan->waves, plan->newton3, st);
+        path_sequence(plan->dseg, &plan->hseg, L, cp, true, 0, plan->waves, plan->newton3, st,
+                      nullptr, plan);
         if (bias)
             run_bias(bias->dev, R, N, plan->hseg.s.Q, G, ek ? ek + 2 : nullptr,
                      step % (uint64_t)bias->stride == 0 ? 1 : 0, cp.status, st);
@@ -780,6 +1056,7 @@ int mop_batch_create(int32_t P, const mop_plan* plans, const int32_t* N, mop_bat
     if (!ctx) return MOP_EINVAL;
     for (int p = 0; p < P; ++p) {
         if (!plans[p] || plans[p]->sys->ctx != ctx || N[p] < 1) return MOP_EINVAL;
+        if (plans[p]->hseg.s.elec != 0) return MOP_EINVAL;
         if (N[p] > plans[p]->max_beads) return MOP_ESIZE;
     }
     if (hipSetDevice(ctx->device) != hipSuccess) return MOP_EHIP;

@@ -15,6 +15,14 @@
 //     same bead (nl: int [lcap] slots of the atoms that passed the search, in search
 //     order; nlc: their count, which may exceed lcap, then the list is incomplete).
 // Per path: FP64 residuals d^n [(N-1)][Q][3], reduction partials, per-bead max |d|^2.
+// Particle-mesh Ewald (systems with Ewald electrostatics), per pair bead:
+//     pgi   int64 [K]      fixed-point accumulation grid of the spreading kernels
+//     pgr   double [K]     real grid (FFT input; also the output of displaced and
+//                          Hessian passes)
+//     pgc   double2 [Kc]   half spectrum (Kc = Kx Ky (Kz/2 + 1))
+//     pphi  double [K]     grid potential of the force pass, kept for the Hessian pass
+//     pep   double [nsb]   energy partials of the solve kernel
+//   plus one FFT work buffer.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -36,6 +44,8 @@ constexpr int32_t DUMMY_KEY = INT32_MIN;
 // Status bits (mirrors MOP_DEV_* of the public header).
 constexpr int ST_NONFINITE = 1;
 constexpr int ST_CAPACITY = 2;
+
+constexpr int PME_BLOCK = 256;    // block size of the grid kernels
 
 struct SysDev {
     int Q, ncx, ncy, ncol, nzb, nt;
@@ -71,6 +81,23 @@ struct SysDev {
     const float4* tab2;   // [nt*nt] {b12 = 168 c12, b6 = -48 c6, c12, c6}
     const float4* tabh;   // [nt*nt] {a12, a6, csf, 0.75 a12}: the Hessian kernel's table
                           // (b12 = -14 a12 and b6 = -8 a6 follow from a12, a6)
+    // electrostatics: 0 reaction field; 1 Ewald real space + particle-mesh reciprocal
+    // part.  With Ewald, crf1 = -psi'(r_c) and e0rf = -psi(r_c) - r_c crf1 for
+    // psi = erfc(beta r)/r, and krf = krf2 = crf = 0.
+    int elec;
+    float ew_beta;        // beta
+    float ew_c2b;         // 2 beta / sqrt(pi)
+    float ew_b2x2;        // 2 beta^2
+    int pme_p;            // B-spline order
+    int Kg[3];            // grid points per axis
+    int Kzh;              // Kz/2 + 1
+    int nsb;              // solve-kernel blocks per bead
+    double kl[3];         // K_a / L_a
+    double qscale;        // fixed-point scale of the charge grid (power of two)
+    double vbound;        // sum |q| * 3 * max K_a/L_a (bound of the dipole grid per unit |v|)
+    double e_const;       // self + neutralising-background energy
+    const double* qd;     // [Q] charges (e)
+    const double* phihat; // [Kx Ky Kzh] f B(m) C(m), half spectrum
 };
 
 // One path (segment) of a launch.  Byte offsets are relative to the workspace base.
@@ -83,7 +110,7 @@ struct SegDev {
     int bpb;              // elementwise blocks per bead: ceil(Q / EWB)
     size_t o_upos, o_umeta, o_orig, o_slotof, o_atomu, o_rank, o_bincnt, o_binoff,
         o_colcnt, o_colstart, o_vs, o_fs, o_f32, o_f32m, o_hv32, o_epart, o_d64, o_rpart,
-        o_dmax, o_eres, o_nl, o_nlc, o_tmpo;
+        o_dmax, o_eres, o_nl, o_nlc, o_tmpo, o_pgi, o_pgr, o_pgc, o_pphi, o_pep, o_pfw;
 };
 
 // Per-launch description, passed by value.

@@ -1,0 +1,302 @@
+"""GPU parity of particle-mesh Ewald systems: the HIP library (Ewald real-space pair
+kernels, fixed-point spreading, rocFFT, FP64 gathers) against the FP64 oracle
+(oracle/potential.py with oracle/pme.py).
+
+Tolerances are those of the reaction-field parity tests (relative L2 per bead: forces
+1e-5, Hessian-vector products 1e-4, gradient 1e-5; energies 1e-6): the reciprocal part
+is FP64 on both sides, so the FP32 real-space pair terms set the error.  A PME energy is
+a small difference of large terms (self energy, excluded-pair corrections, real-space
+pairs: each about as large as the self energy), and the FP32 pair energies carry an
+absolute error of about 1e-8 of those terms, so energies are compared relative to
+|U| + |E_self + E_background| rather than |U|.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import ewald as EW
+from oracle import mop_bias as MB
+from oracle import path as OP
+from oracle import pmd
+from oracle.potential import Model, min_image
+
+pytestmark = pytest.mark.gpu
+
+TOL_F, TOL_HV, TOL_G, TOL_V = 1e-5, 1e-4, 1e-5, 1e-6
+
+
+@pytest.fixture(scope="module")
+def mop():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2501_11962_amd as m
+    m.lib()
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(mop):
+    return mop.Context()
+
+
+def rel(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def cuda(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x, np.float64)).cuda()
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+PME = {
+    "tiny": lambda: W.with_pme(W.tiny()),
+    "cfg1": lambda: W.with_pme(W.cfg1()),
+    "water300": lambda: W.with_pme(W.water_box(300, seed=5, rc=0.6)),
+    "water300_p6": lambda: W.with_pme(W.water_box(300, seed=5, rc=0.6), order=6),
+    "water300_p8": lambda: W.with_pme(W.water_box(300, seed=5, rc=0.6), order=8, spacing=0.1),
+    "cfg2": lambda: W.with_pme(W.cfg2()),
+}
+
+
+@pytest.mark.parametrize("name", list(PME))
+def test_pme_bead_forces_and_energy(name, mop, ctx):
+    s = PME[name]()
+    B = 3
+    R, _, _ = W.random_walk_path(s, B, 11)
+    plan = mop.Plan(mop.System(ctx, s), B)
+    F, U = mop.bead_forces(plan, cuda(R))
+    F, U = F.cpu().numpy(), U.cpu().numpy()
+    assert plan.status() == 0
+    m = Model(s)
+    for b in range(B):
+        Fo, Uo = m.forces(R[b]), m.energy(R[b])
+        ef, eu = rel(F[b], Fo), abs(U[b] - Uo) / (abs(Uo) + abs(m.e_const))
+        say(f"[pme {name}] bead {b}: F relL2 {ef:.2e}, U rel {eu:.2e} (U {Uo:.6e})")
+        assert ef < TOL_F and eu < TOL_V
+
+
+@pytest.mark.parametrize("name", list(PME))
+def test_pme_bead_hvp(name, mop, ctx):
+    s = PME[name]()
+    B = 2
+    R, _, _ = W.random_walk_path(s, B, 12)
+    V = np.random.default_rng(4).normal(0.0, 1e-3, R.shape)
+    plan = mop.Plan(mop.System(ctx, s), B)
+    H = mop.bead_hvp(plan, cuda(R), cuda(V)).cpu().numpy()
+    assert plan.status() == 0
+    m = Model(s)
+    for b in range(B):
+        e = rel(H[b], m.hvp(R[b], V[b]))
+        say(f"[pme {name}] bead {b}: Hv relL2 {e:.2e}")
+        assert e < TOL_HV
+
+
+@pytest.mark.parametrize("name,N", [("tiny", 5), ("cfg1", 8), ("water300", 6), ("cfg2", 6)])
+def test_pme_veff_grad(name, N, mop, ctx):
+    s = PME[name]()
+    R, _, _ = W.random_walk_path(s, N, 13, 0.005 if name == "cfg1" else None)
+    plan = mop.Plan(mop.System(ctx, s), N)
+    G, v = mop.veff_grad(plan, cuda(R))
+    G, v = G.cpu().numpy(), float(v[0])
+    e3 = mop.veff_energy(plan, cuda(R)).cpu().numpy()
+    assert plan.status() == 0
+    m = Model(s)
+    Go, vo = OP.veff_grad(m, R)
+    eg = max(rel(G[n], Go[n]) for n in range(N))
+    ev = abs(v - vo) / (abs(vo) + abs(m.e_const))
+    say(f"[pme {name}] N={N}: G relL2 (worst bead) {eg:.2e}, V_eff rel {ev:.2e}")
+    assert eg < TOL_G
+    assert ev < TOL_V
+    assert e3[0] == v
+
+
+def test_pme_fd_mode_matches_oracle_fd(mop, ctx):
+    s = PME["water300"]()
+    N, h = 5, 1e-4
+    R, _, _ = W.random_walk_path(s, N, 8)
+    plan = mop.Plan(mop.System(ctx, s), N)
+    Gfd, _ = mop.veff_grad(plan, cuda(R), mode=1, fd_h=h)
+    assert plan.status() == 0
+    m = Model(s)
+    Gofd = OP.veff_grad_fd(m, R, h)
+    e = rel(Gfd.cpu().numpy(), Gofd)
+    say(f"[pme fd] gpu-FD vs oracle-FD relL2 {e:.2e}")
+    assert e < 1e-4
+
+
+def test_pme_dipole_scale_edge_cases(mop, ctx):
+    """bead_hvp with a zero vector gives exactly zero; with a vector 1e6 times larger the
+    relative error is unchanged (the fixed-point scale follows max |v|)."""
+    s = PME["water300"]()
+    R, _, _ = W.random_walk_path(s, 2, 14)
+    plan = mop.Plan(mop.System(ctx, s), 2)
+    Z = mop.bead_hvp(plan, cuda(R), cuda(np.zeros_like(R))).cpu().numpy()
+    assert np.all(Z == 0.0)
+    m = Model(s)
+    V = np.random.default_rng(5).normal(0.0, 1.0, R.shape)
+    for scale in (1e-6, 1.0, 1e3):
+        H = mop.bead_hvp(plan, cuda(R), cuda(scale * V)).cpu().numpy()
+        e = rel(H[1], m.hvp(R[1], scale * V[1]))
+        say(f"[pme] |v| scale {scale:g}: Hv relL2 {e:.2e}")
+        assert e < TOL_HV
+    assert plan.status() == 0
+
+
+def test_pme_repeated_calls_bit_identical(mop, ctx):
+    """Integer-atomic spreading keeps PME results identical from call to call."""
+    s = W.with_pme(W.water_box(1002, seed=9, rc=1.0))
+    N = 4
+    R, _, _ = W.random_walk_path(s, N, 29)
+    plan = mop.Plan(mop.System(ctx, s), N)
+    Rt = cuda(R)
+    G0, v0 = (x.cpu().numpy() for x in mop.veff_grad(plan, Rt))
+    F0, U0 = (x.cpu().numpy() for x in mop.bead_forces(plan, Rt))
+    Vt = cuda(np.random.default_rng(3).normal(0.0, 1e-3, R.shape))
+    H0 = mop.bead_hvp(plan, Rt, Vt).cpu().numpy()
+    for _ in range(3):
+        G1, v1 = (x.cpu().numpy() for x in mop.veff_grad(plan, Rt))
+        assert np.array_equal(G0, G1) and np.array_equal(v0, v1)
+        F1, U1 = (x.cpu().numpy() for x in mop.bead_forces(plan, Rt))
+        assert np.array_equal(F0, F1) and np.array_equal(U0, U1)
+        assert np.array_equal(H0, mop.bead_hvp(plan, Rt, Vt).cpu().numpy())
+
+
+def test_pme_graph_replay_matches_eager(mop, ctx):
+    """veff_grad of a PME system (pair kernels, spreading, rocFFT, gathers) captured in
+    one graph; every replay, with eager work between replays, equals the eager call."""
+    import torch
+    s = PME["cfg2"]()
+    N = 5
+    R, _, _ = W.random_walk_path(s, N, 23)
+    plan = mop.Plan(mop.System(ctx, s), N)
+    Rt = cuda(R)
+    G = torch.empty_like(Rt)
+    v = torch.empty(1, dtype=torch.float64, device=Rt.device)
+    mop.veff_grad(plan, Rt, 0, 0.0, G, v)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    cs = torch.cuda.Stream()
+    cs.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.graph(g, stream=cs):
+        ctx.set_stream()
+        mop.veff_grad(plan, Rt, 0, 0.0, G, v)
+    ctx.set_stream()
+    torch.cuda.synchronize()
+    Ge, ve = mop.veff_grad(plan, Rt)
+    Ge, ve = Ge.cpu().numpy(), float(ve[0])
+    for k in range(3):
+        mop.veff_grad(plan, Rt + 1e-3 * (k + 1))
+        torch.cuda.synchronize()
+        G.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        same = np.array_equal(G.cpu().numpy(), Ge) and float(v[0]) == ve
+        say(f"[pme graph] replay {k}: identical to eager: {same}")
+        assert same
+    assert plan.status() == 0
+
+
+def test_pme_biased_path_dynamics(mop, ctx):
+    """Langevin path dynamics with the end-to-end bias on a PME system against the
+    oracle integrator."""
+    s = PME["water300"]()
+    N, steps, tau, kT = 5, 3, 1e-3, 2.494
+    R0, _, _ = W.random_walk_path(s, N, 31, 0.002)
+    V0 = np.random.default_rng(9).normal(0.0, 0.3, R0.shape)
+    A, B = np.arange(0, 6), np.arange(150, 159)
+    plan = mop.Plan(mop.System(ctx, s), N)
+    bias = mop.Bias(plan, A, B, 0.02, 2.0, 4.0, kT, stride=1)
+    R, V = cuda(R0), cuda(V0)
+    G, _ = mop.veff_grad(plan, R)
+    bias.apply(R, G)
+    E = mop.pmd_step(plan, R, V, G, tau, steps, 250.0, kT, seed=5, bias=bias).cpu().numpy()
+    assert plan.status() == 0
+    ob = MB.Bias(A, B, s["mass"], s["box"], 0.02, 2.0, 4.0, kT, stride=1)
+    m = Model(s)
+    Ro, Vo, _, Eo = pmd.run(m, R0, V0, s["mass"], tau, steps, 250.0, kT, 5, 0, ob)
+    e = rel(R.cpu().numpy() - R0, Ro - R0)
+    say(f"[pme pmd] displacement relL2 {e:.2e}; V_eff {E[:, 0]} vs {Eo[:, 0]}")
+    assert e < 1e-6
+    assert np.allclose(E[:, 0], Eo[:, 0], rtol=1e-6, atol=1e-6 * abs(m.e_const))
+    assert np.allclose(E[:, 3], Eo[:, 3], rtol=0, atol=1e-8)
+
+
+def test_pme_parameters_and_restrictions(mop, ctx):
+    s = PME["cfg2"]()
+    sysm = mop.System(ctx, s)
+    grid, beta = sysm.pme_info()
+    assert grid == [int(k) for k in s["pme_grid"]]
+    assert beta == pytest.approx(EW.beta_from_rtol(s["rc"], 1e-5), rel=1e-12)
+    # automatic grid: 2,3,5,7-smooth, >= L/0.12 nm and >= 2 * order
+    s2 = dict(s)
+    s2.pop("pme_grid")
+    g2, _ = mop.System(ctx, s2).pme_info()
+    for k, L in zip(g2, s["box"]):
+        m = k
+        for f in (2, 3, 5, 7):
+            while m % f == 0:
+                m //= f
+        assert m == 1 and k >= L / 0.12 and k >= 8
+    with pytest.raises(mop.MopError):
+        mop.Plan(sysm, 3, newton3=True)
+    plan = mop.Plan(sysm, 3)
+    with pytest.raises(mop.MopError):
+        mop.Batch([plan], [3])
+    rf = mop.System(ctx, W.cfg2())
+    with pytest.raises(mop.MopError):
+        rf.pme_info()
+
+
+def _sampled_forces(m, X, idx):
+    """Oracle forces on atoms idx only: real-space pairs against every atom, excluded-pair
+    corrections, bonds, and the (all-atom) PME reciprocal forces."""
+    F = np.zeros((len(idx), 3))
+    ex = set(m.excluded.tolist())
+    for k, i in enumerate(idx):
+        d = min_image(X - X[i], m.box)
+        r2 = np.einsum("ak,ak->a", d, d)
+        j = np.nonzero((r2 < m.rc ** 2) & (np.arange(m.Q) != i))[0]
+        code = np.minimum(i, j) * m.Q + np.maximum(i, j)
+        keep = np.array([c not in ex for c in code.tolist()], bool)
+        jj = j[keep]
+        r = np.sqrt(r2[jj])
+        g, _ = m.pair_gh(r, np.full(len(jj), i), jj)
+        F[k] = (g[:, None] * d[jj]).sum(0)
+        je = j[~keep]
+        if len(je):
+            from oracle.potential import excl_d1
+            re = np.sqrt(r2[je])
+            ge = excl_d1(re, m.fq * m.q[i] * m.q[je], m.beta) / re
+            F[k] += (ge[:, None] * d[je]).sum(0)
+        for b, (bi, bj) in enumerate(m.bonds):
+            if i in (bi, bj):
+                o = bj if i == bi else bi
+                db = min_image(X[o] - X[i], m.box)
+                br = float(np.sqrt(db @ db))
+                F[k] += m.bond_k[b] * (1.0 - m.bond_r0[b] / br) * db
+    return F + m.pme.forces(X)[idx]
+
+
+def test_pme_cfg4_full_size_sampled(mop, ctx):
+    """The 150,000-atom membrane-shaped workload with PME (grid at 0.12 nm): forces of
+    bead 1 through bead_forces on 48 sampled atoms, and the finiteness of veff_grad over
+    all 16 beads in the benchmark's launch configuration."""
+    s = W.with_pme(W.cfg4())
+    R, _, _ = W.random_walk_path(s, 16, 402)
+    plan = mop.Plan(mop.System(ctx, s), 16)
+    Rt = cuda(R)
+    G, v = mop.veff_grad(plan, Rt)
+    assert plan.status() == 0 and np.isfinite(float(v[0]))
+    F, _ = mop.bead_forces(plan, Rt[:1].contiguous(), want_energy=False)
+    idx = np.random.default_rng(7).choice(s["Q"], 48, replace=False)
+    Fo = _sampled_forces(Model(s), R[0], idx)
+    e = rel(F.cpu().numpy()[0][idx], Fo)
+    say(f"[pme cfg4] sampled bead_forces relL2 {e:.2e}")
+    assert e < TOL_F
