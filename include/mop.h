@@ -90,7 +90,7 @@ typedef struct mop_bias_s* mop_bias;
  *   elec            MOP_ELEC_RF (0, reaction field) or MOP_ELEC_PME (1, particle-mesh
  *                   Ewald; eps_rf is then unused and eps_r divides f as before)
  *   pme_order       B-spline order 4, 6 or 8 (0: 4)
- *   ewald_rtol      erfc(beta r_cut) (0: 1e-5)
+ *   ewald_rtol      erfc(beta r_cut), in [1e-16, 1) (0: 1e-5)
  *   pme_grid[3]     grid points per axis, each >= pme_order, product <= 2^27 (0 for all
  *                   three: the smallest sizes with prime factors 2, 3, 5, 7 that are at
  *                   least L/0.12 nm and at least 2 pme_order)

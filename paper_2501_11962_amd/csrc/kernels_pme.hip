@@ -2,17 +2,23 @@
 // 1995), the long-range method of the paper's standard MD runs (Appendix A.1), with
 // the exact Hessian-vector product the path gradient needs.
 //
-// Per pair bead b (one thread per atom for the particle kernels, grid-stride for the
-// grid kernels):
+// Per pair bead b:
+//   sort     atoms by the grid tile of their base point (counting sort; tiles of about
+//            8^3 points), storing per atom, in tile order, its base point and atom index
+//            (int4) and its fractional offsets and charge (double4): the spreading and
+//            gathering kernels read these contiguously and never divide again.
 //   spread   Q(k) = sum_i q_i theta_i(k)                      (charges, force pass)
 //            dQ(k) = sum_i q_i grad theta_i(k) . v_i           (dipoles, Hessian pass)
 //            theta_i(k) = M_p(u_ix - k_x) M_p(u_iy - k_y) M_p(u_iz - k_z), u = K frac(x/L).
-//            Contributions are rounded to 64-bit fixed point and added with integer
-//            atomics, so the grid (and everything after it) is the same on every call:
-//            the scale is a power of two chosen so that no grid value can overflow
-//            (sum |q| bounds every charge-grid value; sum |q| * 3 max(K/L) max|v_i|
-//            every dipole-grid value).
-//   convert  fixed point -> FP64 real grid (FFT input).
+//            One workgroup owns one tile: an atom with base point b touches points
+//            b - p + 1 .. b along each axis, so the tile's points receive only from atoms
+//            of the tile and of its upper neighbours (8 tiles).  Contributions are
+//            rounded to 64-bit fixed point and summed with LDS integer atomics, so the
+//            grid is the same on every call whatever the order; the owner then writes
+//            its points to the FP64 real grid (no global atomics, no clearing pass).  The
+//            scale is a power of two chosen so that no value can overflow (sum |q|
+//            bounds every charge-grid value; sum |q| * 3 max(K/L) max|v_i| every
+//            dipole-grid value).
 //   FFT      real-to-complex, multiply by f B(m) C(m) (solve, which also forms the
 //            energy 1/2 sum_m f B C |Q^(m)|^2 over the half spectrum), complex-to-real:
 //            phi = the grid potential.
@@ -92,6 +98,27 @@ __device__ __forceinline__ double grid_point(double x, double L, int K, int* idx
     return w;
 }
 
+// Base points and fractional offsets of a position (all three axes).
+__device__ __forceinline__ void grid_base(const SysDev& s, const double x[3], int bse[3],
+                                          double w[3]) {
+    for (int a = 0; a < 3; ++a) {
+        int idx[1];
+        w[a] = grid_point<1>(x[a], s.L[a], s.Kg[a], idx);
+        bse[a] = idx[0];
+    }
+}
+
+// Grid indices base - j (mod K), j = 0..P-1.
+template <int P>
+__device__ __forceinline__ void support(int base, int K, int* idx) {
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+        int k = base - j;
+        if (k < 0) k += K;
+        idx[j] = k;
+    }
+}
+
 // Fixed-point scale of the dipole grid of a bead whose largest |v_i|^2 is m2.
 __device__ __forceinline__ double dipole_scale(const SysDev& s, double m2) {
     if (!(m2 > 0.0) || !isfinite(m2)) return 1.0;
@@ -123,84 +150,225 @@ __device__ __forceinline__ void atom_pos(const SegDev& sg, char* ws, const doubl
 
 }  // namespace
 
-__global__ void __launch_bounds__(PME_BLOCK) k_pme_clear(const SegDev* __restrict__ segs,
-                                                         size_t n, char* ws) {
-    long long* g = wsp<long long>(ws, segs[0].o_pgi);
-    for (size_t k = (size_t)blockIdx.x * PME_BLOCK + threadIdx.x; k < n;
-         k += (size_t)gridDim.x * PME_BLOCK)
-        g[k] = 0;
-}
-
-// KIND 0: charges of R (displaced with fdsign); KIND 1: dipoles q_i v_i (V: [nb][Q][3]).
-template <int P, int KIND>
-__global__ void __launch_bounds__(EWB) k_pme_spread(const SegDev* __restrict__ segs, int nb,
-                                                    char* ws, const double* __restrict__ R,
-                                                    const double* __restrict__ V, int fdsign,
-                                                    double fdh) {
+// Tile of each atom's base point and its rank in the tile (counts zeroed first).
+__global__ void __launch_bounds__(EWB) k_pme_tile_count(const SegDev* __restrict__ segs, int nb,
+                                                        char* ws, const double* __restrict__ R,
+                                                        int fdsign, double fdh) {
     const SegDev& sg = segs[0];
     const SysDev& s = sg.s;
     const int b = blockIdx.x / sg.bpb;
     const int i = (blockIdx.x - b * sg.bpb) * EWB + threadIdx.x;
     if (b >= nb || i >= s.Q) return;
-    double x[3];
+    double x[3], w[3];
     atom_pos(sg, ws, R, b, i, fdsign, fdh, x);
-    int ix[P], iy[P], iz[P];
-    double tx[P], ty[P], tz[P], dx[P], dy[P], dz[P];
-    bspline<P, KIND>(grid_point<P>(x[0], s.L[0], s.Kg[0], ix), tx, dx, nullptr);
-    bspline<P, KIND>(grid_point<P>(x[1], s.L[1], s.Kg[1], iy), ty, dy, nullptr);
-    bspline<P, KIND>(grid_point<P>(x[2], s.L[2], s.Kg[2], iz), tz, dz, nullptr);
-    const size_t Kt = (size_t)s.Kg[0] * s.Kg[1] * s.Kg[2];
-    unsigned long long* g = wsp<unsigned long long>(ws, sg.o_pgi) + (size_t)b * Kt;
-    double c, vx = 0.0, vy = 0.0, vz = 0.0;
-    if (KIND == 0) {
-        c = s.qd[i] * s.qscale;
-    } else {
-        c = s.qd[i] * dipole_scale(s, bead_m2(sg, ws, b));
-        const double* v = V + ((size_t)b * s.Q + i) * 3;
-        vx = v[0] * s.kl[0];
-        vy = v[1] * s.kl[1];
-        vz = v[2] * s.kl[2];
-    }
-#pragma unroll
-    for (int a = 0; a < P; ++a) {
-#pragma unroll
-        for (int e = 0; e < P; ++e) {
-            const size_t row = ((size_t)ix[a] * s.Kg[1] + iy[e]) * s.Kg[2];
-            double pxy, qx = 0.0, qy = 0.0;
-            if (KIND == 0) {
-                pxy = c * tx[a] * ty[e];
-            } else {
-                pxy = c * tx[a] * ty[e] * vz;          // times dz
-                qx = c * dx[a] * ty[e] * vx;           // times tz
-                qy = c * tx[a] * dy[e] * vy;           // times tz
-            }
-#pragma unroll
-            for (int f = 0; f < P; ++f) {
-                const double val = KIND == 0 ? pxy * tz[f] : fma(qx + qy, tz[f], pxy * dz[f]);
-                atomicAdd(g + row + iz[f], (unsigned long long)__double2ll_rn(val));
-            }
-        }
-    }
+    int bse[3];
+    grid_base(s, x, bse, w);
+    const int tile = (s.tile_of[s.tof_off[0] + bse[0]] * s.ntl[1] + s.tile_of[s.tof_off[1] + bse[1]]) *
+                         s.ntl[2] +
+                     s.tile_of[s.tof_off[2] + bse[2]];
+    const int rank = atomicAdd(wsp<int>(ws, sg.o_ptc) + (size_t)b * s.ntile + tile, 1);
+    wsp<int>(ws, sg.o_ptid)[(size_t)b * s.Q + i] = tile;
+    wsp<int>(ws, sg.o_ptrk)[(size_t)b * s.Q + i] = rank;
 }
 
-// Fixed point -> FP64 real grid for beads < nb; zeros for the rest of the FFT batch.
-__global__ void __launch_bounds__(PME_BLOCK) k_pme_convert(const SegDev* __restrict__ segs,
-                                                           int nb, int nbatch, char* ws, int kind) {
+__global__ void __launch_bounds__(PME_BLOCK) k_pme_tile_zero(const SegDev* __restrict__ segs,
+                                                             int n, char* ws) {
+    const int k = blockIdx.x * PME_BLOCK + threadIdx.x;
+    if (k < n) wsp<int>(ws, segs[0].o_ptc)[k] = 0;
+}
+
+// Exclusive scan of the tile counts of one bead per block.
+constexpr int SCAN_BLOCK = 1024;
+__global__ void __launch_bounds__(SCAN_BLOCK) k_pme_tile_scan(const SegDev* __restrict__ segs,
+                                                              char* ws) {
+    __shared__ int wsum[SCAN_BLOCK / 64];
+    __shared__ int carry;
+    const SegDev& sg = segs[0];
+    const int nt = sg.s.ntile;
+    const int b = blockIdx.x;
+    const int* cnt = wsp<const int>(ws, sg.o_ptc) + (size_t)b * nt;
+    int* start = wsp<int>(ws, sg.o_pts) + (size_t)b * (nt + 1);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int base = 0; base < nt; base += SCAN_BLOCK) {
+        const int k = base + threadIdx.x;
+        const int v = k < nt ? cnt[k] : 0;
+        const int incl = wave_incl_scan(v);
+        if (lane == 63) wsum[w] = incl;
+        __syncthreads();
+        int off = carry;
+        for (int u = 0; u < w; ++u) off += wsum[u];
+        if (k < nt) start[k] = off + incl - v;
+        __syncthreads();
+        if (threadIdx.x == SCAN_BLOCK - 1) carry = off + incl;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) start[nt] = carry;
+}
+
+__global__ void __launch_bounds__(EWB) k_pme_tile_scatter(const SegDev* __restrict__ segs, int nb,
+                                                          char* ws, const double* __restrict__ R,
+                                                          int fdsign, double fdh) {
     const SegDev& sg = segs[0];
     const SysDev& s = sg.s;
-    const size_t Kt = (size_t)s.Kg[0] * s.Kg[1] * s.Kg[2];
-    const size_t n = (size_t)nbatch * Kt;
-    const long long* gi = wsp<const long long>(ws, sg.o_pgi);
-    double* gr = wsp<double>(ws, sg.o_pgr);
-    for (size_t k = (size_t)blockIdx.x * PME_BLOCK + threadIdx.x; k < n;
-         k += (size_t)gridDim.x * PME_BLOCK) {
-        const int b = (int)(k / Kt);
-        double v = 0.0;
-        if (b < nb) {
-            const double sc = kind == 0 ? s.qscale : dipole_scale(s, bead_m2(sg, ws, b));
-            v = (double)gi[k] / sc;
+    const int b = blockIdx.x / sg.bpb;
+    const int i = (blockIdx.x - b * sg.bpb) * EWB + threadIdx.x;
+    if (b >= nb || i >= s.Q) return;
+    const size_t o = (size_t)b * s.Q + i;
+    const int tile = wsp<const int>(ws, sg.o_ptid)[o];
+    const int st = wsp<const int>(ws, sg.o_pts)[(size_t)b * (s.ntile + 1) + tile];
+    const size_t slot = (size_t)b * s.Q + st + wsp<const int>(ws, sg.o_ptrk)[o];
+    double x[3], w[3];
+    atom_pos(sg, ws, R, b, i, fdsign, fdh, x);
+    int bse[3];
+    grid_base(s, x, bse, w);
+    wsp<int4>(ws, sg.o_ptb)[slot] = make_int4(bse[0], bse[1], bse[2], i);
+    wsp<double4>(ws, sg.o_ptw)[slot] = make_double4(w[0], w[1], w[2], s.qd[i]);
+}
+
+// One workgroup per (bead, tile): KIND 0 charges of R (displaced with fdsign), KIND 1
+// dipoles q_i v_i (V: [nb][Q][3]).  Beads nb .. nbatch-1 of the FFT batch get zeros.
+constexpr int SPREAD_CAP = 1024;  // candidate list of the spreading kernel (LDS)
+
+template <int P, int KIND>
+__global__ void __launch_bounds__(PME_BLOCK) k_pme_spread(const SegDev* __restrict__ segs, int nb,
+                                                          char* ws, const double* __restrict__ R,
+                                                          const double* __restrict__ V, int fdsign,
+                                                          double fdh) {
+    extern __shared__ unsigned long long acc[];
+    __shared__ int cand_k[SPREAD_CAP], cand_m[SPREAD_CAP];
+    __shared__ int ncand;
+    const SegDev& sg = segs[0];
+    const SysDev& s = sg.s;
+    const int b = blockIdx.x / s.ntile;
+    const int t = blockIdx.x - b * s.ntile;
+    const int tz = t % s.ntl[2], ty = (t / s.ntl[2]) % s.ntl[1], tx = t / (s.ntl[2] * s.ntl[1]);
+    const int lo[3] = {s.tile_lo[s.tlo_off[0] + tx], s.tile_lo[s.tlo_off[1] + ty],
+                       s.tile_lo[s.tlo_off[2] + tz]};
+    const int ex = s.tile_lo[s.tlo_off[0] + tx + 1] - lo[0];
+    const int ey = s.tile_lo[s.tlo_off[1] + ty + 1] - lo[1];
+    const int ez = s.tile_lo[s.tlo_off[2] + tz + 1] - lo[2];
+    const int npts = ex * ey * ez;
+    for (int k = threadIdx.x; k < npts; k += PME_BLOCK) acc[k] = 0ull;
+    __syncthreads();
+    double scale = 1.0;
+    if (b < nb) {
+        scale = KIND == 0 ? s.qscale : dipole_scale(s, bead_m2(sg, ws, b));
+        const int* start = wsp<const int>(ws, sg.o_pts) + (size_t)b * (s.ntile + 1);
+        const int4* pb = wsp<const int4>(ws, sg.o_ptb) + (size_t)b * s.Q;
+        const double4* pw = wsp<const double4>(ws, sg.o_ptw) + (size_t)b * s.Q;
+        // Adds the listed atoms' contributions; lanes hold different atoms.
+        auto flush = [&](int n) {
+            for (int c = threadIdx.x; c < n; c += PME_BLOCK) {
+                const int k = cand_k[c];
+                const unsigned m = (unsigned)cand_m[c];
+                const unsigned mx = m & 0xffu, my = (m >> 8) & 0xffu, mz = (m >> 16) & 0xffu;
+                const int4 ab = pb[k];
+                const int i = ab.w;
+                int ix[P], iy[P], iz[P];
+                support<P>(ab.x, s.Kg[0], ix);
+                support<P>(ab.y, s.Kg[1], iy);
+                support<P>(ab.z, s.Kg[2], iz);
+                const double4 aw = pw[k];
+                double tx_[P], ty_[P], tz_[P], dx_[P], dy_[P], dz_[P];
+                bspline<P, KIND>(aw.x, tx_, dx_, nullptr);
+                bspline<P, KIND>(aw.y, ty_, dy_, nullptr);
+                bspline<P, KIND>(aw.z, tz_, dz_, nullptr);
+                const double c0 = aw.w * scale;
+                double vx = 0.0, vy = 0.0, vz = 0.0;
+                if (KIND == 1) {
+                    const double* v = V + ((size_t)b * s.Q + i) * 3;
+                    vx = v[0] * s.kl[0];
+                    vy = v[1] * s.kl[1];
+                    vz = v[2] * s.kl[2];
+                }
+#pragma unroll
+                for (int a = 0; a < P; ++a) {
+                    if (!((mx >> a) & 1u)) continue;
+#pragma unroll
+                    for (int e = 0; e < P; ++e) {
+                        if (!((my >> e) & 1u)) continue;
+                        const int row = ((ix[a] - lo[0]) * ey + (iy[e] - lo[1])) * ez - lo[2];
+                        double pxy, qx = 0.0, qy = 0.0;
+                        if (KIND == 0) {
+                            pxy = c0 * tx_[a] * ty_[e];
+                        } else {
+                            pxy = c0 * tx_[a] * ty_[e] * vz;     // times dz
+                            qx = c0 * dx_[a] * ty_[e] * vx;      // times tz
+                            qy = c0 * tx_[a] * dy_[e] * vy;      // times tz
+                        }
+#pragma unroll
+                        for (int f = 0; f < P; ++f) {
+                            if (!((mz >> f) & 1u)) continue;
+                            const double val =
+                                KIND == 0 ? pxy * tz_[f] : fma(qx + qy, tz_[f], pxy * dz_[f]);
+                            atomicAdd(acc + row + iz[f], (unsigned long long)__double2ll_rn(val));
+                        }
+                    }
+                }
+            }
+        };
+        if (threadIdx.x == 0) ncand = 0;
+        __syncthreads();
+        const int lane = threadIdx.x & 63;
+        const int nx = s.ntl[0] > 1 ? 2 : 1, ny = s.ntl[1] > 1 ? 2 : 1, nz = s.ntl[2] > 1 ? 2 : 1;
+        for (int n = 0; n < nx * ny * nz; ++n) {
+            const int ux = (tx + n / (ny * nz)) % s.ntl[0];
+            const int uy = (ty + (n / nz) % ny) % s.ntl[1];
+            const int uz = (tz + n % nz) % s.ntl[2];
+            const int u = (ux * s.ntl[1] + uy) * s.ntl[2] + uz;
+            for (int k0 = start[u]; k0 < start[u + 1]; k0 += PME_BLOCK) {
+                // keep the atoms whose spline support meets this tile (list them in LDS)
+                const int k = k0 + threadIdx.x;
+                unsigned m = 0;
+                if (k < start[u + 1]) {
+                    const int4 ab = pb[k];
+                    int ix[P], iy[P], iz[P];
+                    support<P>(ab.x, s.Kg[0], ix);
+                    support<P>(ab.y, s.Kg[1], iy);
+                    support<P>(ab.z, s.Kg[2], iz);
+                    unsigned mx = 0, my = 0, mz = 0;
+#pragma unroll
+                    for (int j = 0; j < P; ++j) {
+                        mx |= (unsigned)(ix[j] >= lo[0] && ix[j] < lo[0] + ex) << j;
+                        my |= (unsigned)(iy[j] >= lo[1] && iy[j] < lo[1] + ey) << j;
+                        mz |= (unsigned)(iz[j] >= lo[2] && iz[j] < lo[2] + ez) << j;
+                    }
+                    if (mx && my && mz) m = mx | (my << 8) | (mz << 16);
+                }
+                const unsigned long long bal = __ballot(m != 0);
+                int base = 0;
+                if (lane == 0 && bal) base = atomicAdd(&ncand, (int)__popcll(bal));
+                base = __shfl(base, 0, 64);
+                if (m) {
+                    const int pos = base + (int)__builtin_amdgcn_mbcnt_hi(
+                                               (unsigned)(bal >> 32),
+                                               __builtin_amdgcn_mbcnt_lo((unsigned)bal, 0u));
+                    cand_k[pos] = k;
+                    cand_m[pos] = (int)m;
+                }
+                __syncthreads();
+                const int nc = ncand;
+                __syncthreads();  // every thread has read the count before it changes again
+                if (nc > SPREAD_CAP - PME_BLOCK) {  // room for one more round of appends
+                    flush(nc);
+                    __syncthreads();
+                    if (threadIdx.x == 0) ncand = 0;
+                    __syncthreads();
+                }
+            }
         }
-        gr[k] = v;
+        flush(ncand);
+    }
+    __syncthreads();
+    const size_t Kt = (size_t)s.Kg[0] * s.Kg[1] * s.Kg[2];
+    double* gr = wsp<double>(ws, sg.o_pgr) + (size_t)b * Kt;
+    const double inv = 1.0 / scale;
+    for (int k = threadIdx.x; k < npts; k += PME_BLOCK) {
+        const int kz = k % ez, ky = (k / ez) % ey, kx = k / (ez * ey);
+        const size_t g = ((size_t)(lo[0] + kx) * s.Kg[1] + (lo[1] + ky)) * s.Kg[2] + lo[2] + kz;
+        gr[g] = b < nb ? (double)(long long)acc[k] * inv : 0.0;
     }
 }
 
@@ -247,16 +415,21 @@ __global__ void __launch_bounds__(EWB) k_pme_gather(const SegDev* __restrict__ s
     const SegDev& sg = segs[0];
     const SysDev& s = sg.s;
     const int b = blockIdx.x / sg.bpb;
-    const int i = (blockIdx.x - b * sg.bpb) * EWB + threadIdx.x;
-    if (b >= nb || i >= s.Q) return;
-    double x[3];
-    atom_pos(sg, ws, R, b, i, fdsign, fdh, x);
+    const int slot = (blockIdx.x - b * sg.bpb) * EWB + threadIdx.x;
+    if (b >= nb || slot >= s.Q) return;
+    // atoms in tile order: the lanes of a wave read neighbouring grid points
+    const int4 ab = wsp<const int4>(ws, sg.o_ptb)[(size_t)b * s.Q + slot];
+    const double4 aw = wsp<const double4>(ws, sg.o_ptw)[(size_t)b * s.Q + slot];
+    const int i = ab.w;
     int ix[P], iy[P], iz[P];
+    support<P>(ab.x, s.Kg[0], ix);
+    support<P>(ab.y, s.Kg[1], iy);
+    support<P>(ab.z, s.Kg[2], iz);
     double tx[P], ty[P], tz[P], dx[P], dy[P], dz[P], hx[P], hy[P], hz[P];
     constexpr int DER = KIND == 0 ? 1 : 2;
-    bspline<P, DER>(grid_point<P>(x[0], s.L[0], s.Kg[0], ix), tx, dx, hx);
-    bspline<P, DER>(grid_point<P>(x[1], s.L[1], s.Kg[1], iy), ty, dy, hy);
-    bspline<P, DER>(grid_point<P>(x[2], s.L[2], s.Kg[2], iz), tz, dz, hz);
+    bspline<P, DER>(aw.x, tx, dx, hx);
+    bspline<P, DER>(aw.y, ty, dy, hy);
+    bspline<P, DER>(aw.z, tz, dz, hz);
     const size_t Kt = (size_t)s.Kg[0] * s.Kg[1] * s.Kg[2];
     const double* phi = wsp<const double>(ws, (KIND == 0 && use_pgr) ? sg.o_pgr : sg.o_pphi) +
                         (size_t)b * Kt;
@@ -268,47 +441,47 @@ __global__ void __launch_bounds__(EWB) k_pme_gather(const SegDev* __restrict__ s
         vy = v[1] * s.kl[1];
         vz = v[2] * s.kl[2];
     }
-    // accumulators: a* = sum grad theta * (phi or dphi); h* = curvature term
+    // Sums over z first (per x-y pair of spline points), 32-bit grid indices:
+    //   St = sum_f phi tz, Sd = sum_f phi dz, Sh = sum_f phi hz, Tt / Td the same of dphi.
+    // Force:  a = sum_{a,e} (dx ty St, tx dy St, tx ty Sd)
+    // H v:    a = sum_{a,e} grad(theta) . dphi + (grad grad theta) v phi, expanded by axis.
     double ax = 0.0, ay = 0.0, az = 0.0;
+    const int K1 = s.Kg[1], K2 = s.Kg[2];
 #pragma unroll
     for (int a = 0; a < P; ++a) {
 #pragma unroll
         for (int e = 0; e < P; ++e) {
-            const size_t row = ((size_t)ix[a] * s.Kg[1] + iy[e]) * s.Kg[2];
+            const int row = (ix[a] * K1 + iy[e]) * K2;
             const double txy = tx[a] * ty[e], dxy = dx[a] * ty[e], xdy = tx[a] * dy[e];
-            double hxx = 0.0, hyy = 0.0, hxy = 0.0;
-            if (KIND == 1) {
-                hxx = hx[a] * ty[e];
-                hyy = tx[a] * hy[e];
-                hxy = dx[a] * dy[e];
-            }
+            double St = 0.0, Sd = 0.0, Sh = 0.0, Tt = 0.0, Td = 0.0;
 #pragma unroll
             for (int f = 0; f < P; ++f) {
-                const size_t k = row + iz[f];
-                if (KIND == 0) {
-                    const double p = phi[k];
-                    ax = fma(dxy * tz[f], p, ax);
-                    ay = fma(xdy * tz[f], p, ay);
-                    az = fma(txy * dz[f], p, az);
-                } else {
-                    const double p = phi[k], q = dphi[k];
-                    // grad theta . dphi (per unit u; K/L applied below)
-                    const double gx = dxy * tz[f], gy = xdy * tz[f], gz = txy * dz[f];
-                    // (grad grad theta) v per unit u (v already scaled by K/L)
-                    const double cx = hxx * tz[f] * vx + hxy * tz[f] * vy + dx[a] * ty[e] * dz[f] * vz;
-                    const double cy = hxy * tz[f] * vx + hyy * tz[f] * vy + tx[a] * dy[e] * dz[f] * vz;
-                    const double cz = dxy * dz[f] * vx + xdy * dz[f] * vy + txy * hz[f] * vz;
-                    ax = fma(gx, q, fma(cx, p, ax));
-                    ay = fma(gy, q, fma(cy, p, ay));
-                    az = fma(gz, q, fma(cz, p, az));
+                const double p = phi[row + iz[f]];
+                St = fma(p, tz[f], St);
+                Sd = fma(p, dz[f], Sd);
+                if (KIND == 1) {
+                    const double q = dphi[row + iz[f]];
+                    Sh = fma(p, hz[f], Sh);
+                    Tt = fma(q, tz[f], Tt);
+                    Td = fma(q, dz[f], Td);
                 }
+            }
+            if (KIND == 0) {
+                ax = fma(dxy, St, ax);
+                ay = fma(xdy, St, ay);
+                az = fma(txy, Sd, az);
+            } else {
+                const double hxx = hx[a] * ty[e], hyy = tx[a] * hy[e], hxy = dx[a] * dy[e];
+                ax = fma(dxy, Tt, fma(fma(hxx, vx, hxy * vy), St, fma(dxy * vz, Sd, ax)));
+                ay = fma(xdy, Tt, fma(fma(hxy, vx, hyy * vy), St, fma(xdy * vz, Sd, ay)));
+                az = fma(txy, Td, fma(fma(dxy, vx, xdy * vy), Sd, fma(txy * vz, Sh, az)));
             }
         }
     }
     (void)hx;
     (void)hy;
     (void)hz;
-    const double qi = s.qd[i];
+    const double qi = aw.w;
     double o[3];
     if (KIND == 0) {
         o[0] = -qi * s.kl[0] * ax;
@@ -355,19 +528,17 @@ __global__ void __launch_bounds__(EWB) k_pme_vmax(const SegDev* __restrict__ seg
 
 namespace {
 
-int grid_blocks(size_t n) {
-    const size_t b = (n + PME_BLOCK - 1) / PME_BLOCK;
-    return (int)std::min<size_t>(b, 8192);
-}
-
 template <int P>
-void spread_p(const SegDev* dsegs, const SegDev& h, int nb, char* ws, const double* R,
+void spread_p(const SegDev* dsegs, const SegDev& h, int nb, int nbatch, char* ws, const double* R,
               const double* V, int kind, int fdsign, double fdh, hipStream_t st) {
-    const dim3 grid(nb * h.bpb);
+    const dim3 grid(nbatch * h.s.ntile);
+    const size_t lds = (size_t)h.s.tile_pts * sizeof(unsigned long long);
     if (kind == 0)
-        hipLaunchKernelGGL((k_pme_spread<P, 0>), grid, dim3(EWB), 0, st, dsegs, nb, ws, R, V, fdsign, fdh);
+        hipLaunchKernelGGL((k_pme_spread<P, 0>), grid, dim3(PME_BLOCK), lds, st, dsegs, nb, ws, R, V,
+                           fdsign, fdh);
     else
-        hipLaunchKernelGGL((k_pme_spread<P, 1>), grid, dim3(EWB), 0, st, dsegs, nb, ws, R, V, fdsign, fdh);
+        hipLaunchKernelGGL((k_pme_spread<P, 1>), grid, dim3(PME_BLOCK), lds, st, dsegs, nb, ws, R, V,
+                           fdsign, fdh);
 }
 
 template <int P>
@@ -385,23 +556,26 @@ void gather_p(const SegDev* dsegs, const SegDev& h, int nb, char* ws, const doub
 
 }  // namespace
 
-void run_pme_spread(const SegDev* dsegs, const SegDev& h, int nb, char* ws, const double* R,
-                    const double* V, int kind, int fdsign, double fdh, hipStream_t st) {
-    const size_t Kt = (size_t)h.s.Kg[0] * h.s.Kg[1] * h.s.Kg[2];
-    hipLaunchKernelGGL(k_pme_clear, dim3(grid_blocks((size_t)nb * Kt)), dim3(PME_BLOCK), 0, st,
-                       dsegs, (size_t)nb * Kt, ws);
-    switch (h.s.pme_p) {
-        case 6: spread_p<6>(dsegs, h, nb, ws, R, V, kind, fdsign, fdh, st); break;
-        case 8: spread_p<8>(dsegs, h, nb, ws, R, V, kind, fdsign, fdh, st); break;
-        default: spread_p<4>(dsegs, h, nb, ws, R, V, kind, fdsign, fdh, st); break;
-    }
+void run_pme_sort(const SegDev* dsegs, const SegDev& h, int nb, char* ws, const double* R,
+                  int fdsign, double fdh, hipStream_t st) {
+    const int n = nb * h.s.ntile;
+    hipLaunchKernelGGL(k_pme_tile_zero, dim3((n + PME_BLOCK - 1) / PME_BLOCK), dim3(PME_BLOCK), 0, st,
+                       dsegs, n, ws);
+    hipLaunchKernelGGL(k_pme_tile_count, dim3(nb * h.bpb), dim3(EWB), 0, st, dsegs, nb, ws, R, fdsign,
+                       fdh);
+    hipLaunchKernelGGL(k_pme_tile_scan, dim3(nb), dim3(SCAN_BLOCK), 0, st, dsegs, ws);
+    hipLaunchKernelGGL(k_pme_tile_scatter, dim3(nb * h.bpb), dim3(EWB), 0, st, dsegs, nb, ws, R,
+                       fdsign, fdh);
 }
 
-void run_pme_convert(const SegDev* dsegs, const SegDev& h, int nb, int nbatch, char* ws, int kind,
-                     hipStream_t st) {
-    const size_t Kt = (size_t)h.s.Kg[0] * h.s.Kg[1] * h.s.Kg[2];
-    hipLaunchKernelGGL(k_pme_convert, dim3(grid_blocks((size_t)nbatch * Kt)), dim3(PME_BLOCK), 0, st,
-                       dsegs, nb, nbatch, ws, kind);
+void run_pme_spread(const SegDev* dsegs, const SegDev& h, int nb, int nbatch, char* ws,
+                    const double* R, const double* V, int kind, int fdsign, double fdh,
+                    hipStream_t st) {
+    switch (h.s.pme_p) {
+        case 6: spread_p<6>(dsegs, h, nb, nbatch, ws, R, V, kind, fdsign, fdh, st); break;
+        case 8: spread_p<8>(dsegs, h, nb, nbatch, ws, R, V, kind, fdsign, fdh, st); break;
+        default: spread_p<4>(dsegs, h, nb, nbatch, ws, R, V, kind, fdsign, fdh, st); break;
+    }
 }
 
 void run_pme_solve(const SegDev* dsegs, const SegDev& h, int nb, char* ws, int want_e,

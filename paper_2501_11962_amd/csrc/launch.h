@@ -51,11 +51,14 @@ void run_pmd_post(const SegDev* dsegs, const SegDev* hsegs, const Launch& base, 
 
 // Particle-mesh Ewald (single-path launches; nb pair beads).  kind 0: charges / forces,
 // kind 1: dipoles q v / Hessian-vector product.  fdsign != 0 displaces R by fdsign * eps d
-// (finite-difference term).  Spreading clears the fixed-point grid first.
-void run_pme_spread(const SegDev* dsegs, const SegDev& h, int nb, char* ws, const double* R,
-                    const double* V, int kind, int fdsign, double fdh, hipStream_t st);
-void run_pme_convert(const SegDev* dsegs, const SegDev& h, int nb, int nbatch, char* ws, int kind,
-                     hipStream_t st);
+// (finite-difference term).  run_pme_sort orders the atoms by grid tile (needed by the
+// spread and gather of the same configuration); run_pme_spread writes the FP64 real grid
+// of beads < nb and zeros for beads nb .. nbatch-1 of the FFT batch.
+void run_pme_sort(const SegDev* dsegs, const SegDev& h, int nb, char* ws, const double* R,
+                  int fdsign, double fdh, hipStream_t st);
+void run_pme_spread(const SegDev* dsegs, const SegDev& h, int nb, int nbatch, char* ws,
+                    const double* R, const double* V, int kind, int fdsign, double fdh,
+                    hipStream_t st);
 void run_pme_solve(const SegDev* dsegs, const SegDev& h, int nb, char* ws, int want_e,
                    hipStream_t st);
 // outsel: 0 f32, 1 hv32, 2 f32m; use_pgr: kind-0 potential read from pgr instead of pphi.

@@ -118,7 +118,9 @@ static int check_desc(const mop_system_desc* d) {
     if (d->elec == MOP_ELEC_PME) {
         const int p = d->pme_order ? d->pme_order : 4;
         if (p != 4 && p != 6 && p != 8) return MOP_EINVAL;
-        if (!(d->ewald_rtol >= 0.0 && d->ewald_rtol < 1.0)) return MOP_EINVAL;
+        // beta r_c <= 6 (the range of the pair kernels' erfc): rtol >= erfc(6) = 2.2e-17
+        if (!(d->ewald_rtol == 0.0 || (d->ewald_rtol >= 1e-16 && d->ewald_rtol < 1.0)))
+            return MOP_EINVAL;
         const int* g = d->pme_grid;
         const bool autog = g[0] == 0 && g[1] == 0 && g[2] == 0;
         if (!autog) {
@@ -283,11 +285,17 @@ static size_t layout(SegDev& sg, int maxb, int maxN, size_t base) {
         take(sg.o_nl, B * s.cpb * (size_t)s.lcap * 4);
         take(sg.o_nlc, B * s.cpb * 4);
     }
-    sg.o_pgi = sg.o_pgr = sg.o_pgc = sg.o_pphi = sg.o_pep = sg.o_pfw = 0;
+    sg.o_ptc = sg.o_pts = sg.o_ptid = sg.o_ptrk = sg.o_ptb = sg.o_ptw = 0;
+    sg.o_pgr = sg.o_pgc = sg.o_pphi = sg.o_pep = sg.o_pfw = 0;
     if (s.elec == 1) {
         const size_t Kt = (size_t)s.Kg[0] * s.Kg[1] * s.Kg[2];
         const size_t Kc = (size_t)s.Kg[0] * s.Kg[1] * s.Kzh;
-        take(sg.o_pgi, B * Kt * 8);
+        take(sg.o_ptc, B * (size_t)s.ntile * 4);
+        take(sg.o_pts, B * (size_t)(s.ntile + 1) * 4);
+        take(sg.o_ptid, B * Q * 4);
+        take(sg.o_ptrk, B * Q * 4);
+        take(sg.o_ptb, B * Q * 16);
+        take(sg.o_ptw, B * Q * 32);
         take(sg.o_pgr, B * Kt * 8);
         take(sg.o_pgc, B * Kc * 16);
         take(sg.o_pphi, B * Kt * 8);
@@ -435,6 +443,7 @@ int mop_system_create(mop_ctx ctx, const mop_system_desc* d, mop_system* out) {
     s.e0rf = (float)(-rc * crf1);
     s.elec = d->elec;
     std::vector<double> phihat;
+    std::vector<int> tile_lo, tile_of;
     if (d->elec == MOP_ELEC_PME) {
         // Ewald real space: psi = erfc(beta r)/r, shifted-force at r_c
         const double rtol = d->ewald_rtol > 0.0 ? d->ewald_rtol : 1e-5;
@@ -491,6 +500,24 @@ int mop_system_create(mop_ctx ctx, const mop_system_desc* d, mop_system* out) {
                             std::exp(-PI * PI * m2 / (beta * beta)) / (PI * V * m2);
                     phihat[((size_t)mx * s.Kg[1] + my) * s.Kzh + mz] = v;
                 }
+        // spreading tiles: about PME_TILE points per edge, balanced
+        int maxe[3];
+        for (int a = 0; a < 3; ++a) {
+            const int K = s.Kg[a];
+            const int nt = std::max(1, K / PME_TILE);
+            s.ntl[a] = nt;
+            s.tlo_off[a] = (int)tile_lo.size();
+            s.tof_off[a] = (int)tile_of.size();
+            maxe[a] = 0;
+            for (int t = 0; t <= nt; ++t) tile_lo.push_back((int)((long long)t * K / nt));
+            for (int t = 0; t < nt; ++t) {
+                const int a0 = tile_lo[s.tlo_off[a] + t], a1 = tile_lo[s.tlo_off[a] + t + 1];
+                maxe[a] = std::max(maxe[a], a1 - a0);
+                for (int k = a0; k < a1; ++k) tile_of.push_back(t);
+            }
+        }
+        s.ntile = s.ntl[0] * s.ntl[1] * s.ntl[2];
+        s.tile_pts = maxe[0] * maxe[1] * maxe[2];
     }
     // per atom
     std::vector<float> qs(Q);
@@ -561,6 +588,8 @@ int mop_system_create(mop_ctx ctx, const mop_system_desc* d, mop_system* out) {
     if (!e) e = upload(sys, tabh.data(), tabh.size(), &s.tabh);
     if (!e && s.elec == 1) e = upload(sys, d->charge, Q, &s.qd);
     if (!e && s.elec == 1) e = upload(sys, phihat.data(), phihat.size(), &s.phihat);
+    if (!e && s.elec == 1) e = upload(sys, tile_lo.data(), tile_lo.size(), &s.tile_lo);
+    if (!e && s.elec == 1) e = upload(sys, tile_of.data(), tile_of.size(), &s.tile_of);
     if (e) {
         mop_system_destroy(sys);
         return e;
@@ -736,8 +765,8 @@ static void pme_forces(const mop_plan_s* pl, int nb, const CallPtrs& cp, int fds
                        bool gather, hipStream_t st) {
     const SegDev& h = pl->hseg;
     char* ws = cp.ws;
-    run_pme_spread(pl->dseg, h, nb, ws, cp.R, nullptr, 0, fdsign, cp.fd_h, st);
-    run_pme_convert(pl->dseg, h, nb, h.maxb, ws, 0, st);
+    run_pme_sort(pl->dseg, h, nb, ws, cp.R, fdsign, cp.fd_h, st);
+    run_pme_spread(pl->dseg, h, nb, h.maxb, ws, cp.R, nullptr, 0, fdsign, cp.fd_h, st);
     run_fft(pl->fft, true, ws + h.o_pgr, ws + h.o_pgc, ws + h.o_pfw, st);
     run_pme_solve(pl->dseg, h, nb, ws, fdsign == 0 ? 1 : 0, st);
     run_fft(pl->fft, false, ws + h.o_pgc, ws + (fdsign == 0 ? h.o_pphi : h.o_pgr), ws + h.o_pfw, st);
@@ -746,14 +775,13 @@ static void pme_forces(const mop_plan_s* pl, int nb, const CallPtrs& cp, int fds
                        fdsign != 0 ? 1 : 0, st);
 }
 
-// PME reciprocal H v of nb pair beads (V: [nb][Q][3]; needs pphi of the same beads and
-// the per-bead max |v|^2), added to hv32.
+// PME reciprocal H v of nb pair beads (V: [nb][Q][3]; needs pphi and the tile order of
+// the same beads from pme_forces, and the per-bead max |v|^2), added to hv32.
 static void pme_hvp(const mop_plan_s* pl, int nb, const CallPtrs& cp, const double* V,
                     hipStream_t st) {
     const SegDev& h = pl->hseg;
     char* ws = cp.ws;
-    run_pme_spread(pl->dseg, h, nb, ws, cp.R, V, 1, 0, 0.0, st);
-    run_pme_convert(pl->dseg, h, nb, h.maxb, ws, 1, st);
+    run_pme_spread(pl->dseg, h, nb, h.maxb, ws, cp.R, V, 1, 0, 0.0, st);
     run_fft(pl->fft, true, ws + h.o_pgr, ws + h.o_pgc, ws + h.o_pfw, st);
     run_pme_solve(pl->dseg, h, nb, ws, 0, st);
     run_fft(pl->fft, false, ws + h.o_pgc, ws + h.o_pgr, ws + h.o_pfw, st);

@@ -16,7 +16,10 @@
 //     order; nlc: their count, which may exceed lcap, then the list is incomplete).
 // Per path: FP64 residuals d^n [(N-1)][Q][3], reduction partials, per-bead max |d|^2.
 // Particle-mesh Ewald (systems with Ewald electrostatics), per pair bead:
-//     pgi   int64 [K]      fixed-point accumulation grid of the spreading kernels
+//     ptc   int [ntile]    atoms per grid tile; pts int [ntile + 1] their starts
+//     ptid, ptrk int [Q]   tile and rank of each atom
+//     ptb   int4 [Q]       in tile order: base grid point (x, y, z) and atom index
+//     ptw   double4 [Q]    in tile order: fractional offsets (x, y, z) and charge
 //     pgr   double [K]     real grid (FFT input; also the output of displaced and
 //                          Hessian passes)
 //     pgc   double2 [Kc]   half spectrum (Kc = Kx Ky (Kz/2 + 1))
@@ -46,6 +49,7 @@ constexpr int ST_NONFINITE = 1;
 constexpr int ST_CAPACITY = 2;
 
 constexpr int PME_BLOCK = 256;    // block size of the grid kernels
+constexpr int PME_TILE = 8;       // nominal grid tile edge of the spreading kernel
 
 struct SysDev {
     int Q, ncx, ncy, ncol, nzb, nt;
@@ -98,6 +102,13 @@ struct SysDev {
     double e_const;       // self + neutralising-background energy
     const double* qd;     // [Q] charges (e)
     const double* phihat; // [Kx Ky Kzh] f B(m) C(m), half spectrum
+    // grid tiles of the spreading kernel: ntl[a] tiles per axis with edges
+    // tile_lo[tlo_off[a] + t] (balanced, each at least PME_TILE points unless the axis is
+    // shorter), tile_of[tof_off[a] + k] the tile of grid index k; tile_pts = largest tile
+    int ntl[3], ntile, tile_pts;
+    int tlo_off[3], tof_off[3];
+    const int* tile_lo;
+    const int* tile_of;
 };
 
 // One path (segment) of a launch.  Byte offsets are relative to the workspace base.
@@ -110,7 +121,8 @@ struct SegDev {
     int bpb;              // elementwise blocks per bead: ceil(Q / EWB)
     size_t o_upos, o_umeta, o_orig, o_slotof, o_atomu, o_rank, o_bincnt, o_binoff,
         o_colcnt, o_colstart, o_vs, o_fs, o_f32, o_f32m, o_hv32, o_epart, o_d64, o_rpart,
-        o_dmax, o_eres, o_nl, o_nlc, o_tmpo, o_pgi, o_pgr, o_pgc, o_pphi, o_pep, o_pfw;
+        o_dmax, o_eres, o_nl, o_nlc, o_tmpo, o_ptc, o_pts, o_ptid, o_ptrk, o_ptb, o_ptw, o_pgr, o_pgc,
+        o_pphi, o_pep, o_pfw;
 };
 
 // Per-launch description, passed by value.

@@ -97,3 +97,33 @@ def test_calls_reject_null_handles(mop):
     assert L.veff_energy(None, None, 1, None, None, None, None) == -1
     assert L.bead_hvp(None, None, None, 1, None, None) == -1
     assert L.mop_batch_create(0, None, None, C.byref(C.c_void_p())) == -1
+
+
+def test_system_check_pme(mop):
+    s = W.tiny()
+    assert mop.system_check(W.with_pme(s)) == 0
+    assert mop.system_check(W.with_pme(s, order=8)) == 0
+    assert mop.system_check(dict(W.with_pme(s), pme_grid=None)) == 0        # automatic grid
+    assert mop.system_check(W.with_pme(s, order=5)) == -1                   # odd order
+    assert mop.system_check(W.with_pme(s, grid=[14, 14, 3])) == -1          # below the order
+    assert mop.system_check(W.with_pme(s, grid=[1024, 1024, 256])) == -1    # too many points
+    assert mop.system_check(W.with_pme(s, rtol=1.0)) == -1
+    with pytest.raises(ValueError):
+        mop.system_check(dict(s, elec="coulomb"))
+
+
+def test_ewald_erfc_constants_match_their_fit():
+    """The Ewald pair kernels' erfc polynomial is the one erfc_fit.py produces, and its
+    FP32 evaluation stays within 4e-7 relative error of erfc on 0 <= x <= 6."""
+    from scipy.special import erfc
+    from paper_2501_11962_amd import erfc_fit as EF
+    src = open(os.path.join(ROOT, "paper_2501_11962_amd", "csrc", "kernels_pair.hip")).read()
+    body = src[src.index("float erfc_ex2("):]
+    body = body[:body.index("return")]
+    consts = [float(v) for v in re.findall(r"(-?\d\.\d+e[-+]\d+)f", body)]
+    x, _, coef = EF.fit()
+    assert len(consts) == EF.DEG + 1
+    assert np.allclose(consts[::-1], coef, rtol=1e-8, atol=0)
+    p = EF.eval_f32(np.array(consts[::-1]), x).astype(np.float64)
+    e = np.abs(np.exp(-x * x) * p - erfc(x)) / erfc(x)
+    assert e.max() < 4e-7
