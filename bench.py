@@ -432,7 +432,7 @@ def main():
     t_hvp, t_force = phases["hvp"] * 1e-3, phases["force"] * 1e-3
     ach = flops_hvp / t_hvp / 1e12
     traffic = traffic_from_profiles(args.config)
-    roof = dict(bound="alu", kernel="k_pair<1> (pair Hessian-vector product)",
+    roof = dict(bound="alu", kernel="k_pair<1,4,0,0> (pair Hessian-vector product)",
                 achieved=round(ach, 3), peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
                 frac=round(ach / PEAK_FP32_TFLOPS, 4), traffic=traffic,
                 algorithmic_flops_per_launch=flops_hvp, pairs_per_bead=npairs,
