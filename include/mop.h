@@ -204,7 +204,10 @@ int veff_energy(mop_plan plan, const double* R, int32_t N, double* veff, double*
  * double, or NULL).  mode 0: exact Hessian-vector products.  mode 1: the
  * finite-difference term of eq. (5), [F(R + eps d) - F(R - eps d)]/(4 eps), with
  * eps = fd_h / max_i |d^n_i| per bead (fd_h in nm, > 0), each displaced configuration
- * re-binned.  G = -F_eff of eqs. (5)-(7).
+ * re-binned.  mode 2: the same finite differences with the binning of R kept for the
+ * displaced configurations (only the coordinates are rewritten); exact for fd_h up to
+ * the neighbour search margin (1e-4 nm); beyond it, pairs that cross the cut-off during
+ * the displacement may be missed.  G = -F_eff of eqs. (5)-(7).
  */
 int veff_grad(mop_plan plan, const double* R, int32_t N, double* G, double* veff,
               int32_t mode, double fd_h, void* ws);
@@ -319,7 +322,7 @@ int mop_status_clear(mop_plan plan, void* ws);
 #define MOP_PHASE_FORCE 1     /* pair-force kernel, beads 1..N-1 (energy of bead 1) */
 #define MOP_PHASE_RESID 2     /* residuals, spring energy, FP32 copy of d */
 #define MOP_PHASE_HVP 3       /* pair Hessian-vector kernel (mode 0) */
-#define MOP_PHASE_FD 4        /* re-binning + two force passes (mode 1) */
+#define MOP_PHASE_FD 4        /* (re-)binning + two force passes (modes 1, 2) */
 #define MOP_PHASE_ASSEMBLE 5  /* gradient assembly and V_eff reduction */
 int veff_grad_timed(mop_plan plan, const double* R, int32_t N, double* G, double* veff,
                     int32_t mode, double fd_h, void* ws, float* phase_ms);

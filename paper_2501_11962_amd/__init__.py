@@ -323,7 +323,8 @@ def veff_energy(plan, R):
 
 
 def veff_grad(plan, R, mode=0, fd_h=1e-4, G=None, veff=None):
-    """(G, V_eff): G (N, Q, 3) float64 = grad V_eff; mode 0 exact HVP, 1 finite differences."""
+    """(G, V_eff): G (N, Q, 3) float64 = grad V_eff; mode 0 exact HVP, 1 finite differences
+    (displaced configurations re-binned), 2 finite differences on the binning of R."""
     torch = _torch()
     _dev_tensor(R, torch.float64)
     if G is None:

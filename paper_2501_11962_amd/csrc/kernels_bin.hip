@@ -199,6 +199,43 @@ __global__ void __launch_bounds__(EWB) k_bin_pad(const SegDev* __restrict__ segs
     }
 }
 
+// Shared-bin finite differences: the displaced coordinates R^b + fdsign eps_b d^b written
+// into the slots the binning of R gave each atom (no new sort).
+__global__ void __launch_bounds__(EWB) k_bin_displace(const SegDev* __restrict__ segs, Launch L,
+                                                      char* ws, const double* __restrict__ R,
+                                                      int fdsign, double fdh) {
+    const int blk = blockIdx.x;
+    const int p = find_seg(L, blk);
+    const SegDev& sg = segs[p];
+    const int local = blk - L.pf[p];
+    const int b = local / sg.bpb;
+    const int i = (local - b * sg.bpb) * EWB + threadIdx.x;
+    const int Q = sg.s.Q;
+    if (i >= Q) return;
+    const double* r = R + sg.roff + ((size_t)b * Q + i) * 3;
+    const double m2 = __longlong_as_double((long long)wsp<unsigned long long>(ws, sg.o_dmax)[b]);
+    const double eps = m2 > 0.0 ? fdsign * fdh / sqrt(m2) : 0.0;
+    const double* d = wsp<const double>(ws, sg.o_d64) + ((size_t)b * Q + i) * 3;
+    const int slot = wsp<const int>(ws, sg.o_slotof)[(size_t)b * Q + i];
+    wsp<uint4>(ws, sg.o_upos)[(size_t)b * sg.s.S + slot] =
+        make_uint4(to_fixed(r[0] + eps * d[0], sg.s.L[0]), to_fixed(r[1] + eps * d[1], sg.s.L[1]),
+                   to_fixed(r[2] + eps * d[2], sg.s.L[2]), __float_as_uint(sg.s.qs[i]));
+}
+
+void run_displace(const SegDev* dsegs, const SegDev* hsegs, const Launch& base, char* ws,
+                  const double* R, int fdsign, double fdh, hipStream_t st) {
+    Launch La = base;
+    La.pf[0] = 0;
+    for (int p = 0; p < base.nseg; ++p) La.pf[p + 1] = La.pf[p] + base.nb[p] * hsegs[p].bpb;
+    hipLaunchKernelGGL(k_bin_displace, dim3(La.pf[base.nseg]), dim3(EWB), 0, st, dsegs, La, ws, R,
+                       fdsign, fdh);
+    Launch Lc = base;
+    Lc.pf[0] = 0;
+    for (int p = 0; p < base.nseg; ++p)
+        Lc.pf[p + 1] = Lc.pf[p] + (base.nb[p] * hsegs[p].s.ncol + EWB - 1) / EWB;
+    hipLaunchKernelGGL(k_bin_pad, dim3(Lc.pf[base.nseg]), dim3(EWB), 0, st, dsegs, Lc, ws);
+}
+
 void run_binning(const SegDev* dsegs, const SegDev* hsegs, const Launch& base, char* ws,
                  const double* R, int fdsign, double fdh, hipStream_t st) {
     Launch L = base;

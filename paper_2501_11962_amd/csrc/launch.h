@@ -9,6 +9,11 @@ namespace mop {
 void run_binning(const SegDev* dsegs, const SegDev* hsegs, const Launch& base, char* ws,
                  const double* R, int fdsign, double fdh, hipStream_t st);
 
+// Shared-bin finite differences: rewrite the coordinates of the current slots with
+// R + fdsign * eps d (binning of R kept).
+void run_displace(const SegDev* dsegs, const SegDev* hsegs, const Launch& base, char* ws,
+                  const double* R, int fdsign, double fdh, hipStream_t st);
+
 // Pair kernels.  mode 0: forces into f32 (outsel 0), hv32 (outsel 1) or f32m (outsel 2);
 // energy_bead: -1 none, -2 every bead, b >= 0 that bead only.  mode 1: H v from vs into hv32.
 // newton3: each pair once with atomics (1) or from both sides without atomics (0).

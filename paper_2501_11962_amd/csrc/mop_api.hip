@@ -860,16 +860,17 @@ static void path_sequence(const SegDev* dsegs, const SegDev* hsegs, const Launch
             if (pme) pme_hvp(pl, Lh.nb[0], cp, wsp_host<double>(cp.ws, hsegs[0].o_d64), st);
         }
         mark(4);
-        if (any && mode == 1) {
-            run_binning(dsegs, hsegs, Lh, cp.ws, cp.R, +1, cp.fd_h, st);
-            run_pair(dsegs, hsegs, Lh, cp.ws, 0, 1, -1, waves, n3, st);
-            if (pme) pme_forces(pl, Lh.nb[0], cp, +1, 1, true, st);
-            run_binning(dsegs, hsegs, Lh, cp.ws, cp.R, -1, cp.fd_h, st);
-            run_pair(dsegs, hsegs, Lh, cp.ws, 0, 2, -1, waves, n3, st);
-            if (pme) pme_forces(pl, Lh.nb[0], cp, -1, 2, true, st);
+        if (any && mode != 0) {
+            // mode 1 re-bins each displaced configuration; mode 2 keeps R's binning
+            for (int sgn : {+1, -1}) {
+                if (mode == 1) run_binning(dsegs, hsegs, Lh, cp.ws, cp.R, sgn, cp.fd_h, st);
+                else run_displace(dsegs, hsegs, Lh, cp.ws, cp.R, sgn, cp.fd_h, st);
+                run_pair(dsegs, hsegs, Lh, cp.ws, 0, sgn > 0 ? 1 : 2, -1, waves, n3, st);
+                if (pme) pme_forces(pl, Lh.nb[0], cp, sgn, sgn > 0 ? 1 : 2, true, st);
+            }
         }
         mark(5);
-        run_assemble(dsegs, hsegs, base, cp, mode, st);
+        run_assemble(dsegs, hsegs, base, cp, mode != 0 ? 1 : 0, st);
     } else {
         mark(4);
         mark(5);
@@ -897,8 +898,8 @@ int veff_energy(mop_plan plan, const double* R, int32_t N, double* veff, double*
 int veff_grad(mop_plan plan, const double* R, int32_t N, double* G, double* veff, int32_t mode,
               double fd_h, void* ws) {
     if (!plan || !R || !G || !ws) return MOP_EINVAL;
-    if (N < 1 || (mode != 0 && mode != 1)) return MOP_EINVAL;
-    if (mode == 1 && !(fd_h > 0.0)) return MOP_EINVAL;
+    if (N < 1 || mode < 0 || mode > 2) return MOP_EINVAL;
+    if (mode != 0 && !(fd_h > 0.0)) return MOP_EINVAL;
     if (N > plan->max_beads) return MOP_ESIZE;
     CallPtrs cp = call_ptrs(ws);
     cp.R = R;
@@ -914,8 +915,8 @@ int veff_grad(mop_plan plan, const double* R, int32_t N, double* G, double* veff
 int veff_grad_timed(mop_plan plan, const double* R, int32_t N, double* G, double* veff,
                     int32_t mode, double fd_h, void* ws, float* phase_ms) {
     if (!plan || !R || !G || !ws || !phase_ms) return MOP_EINVAL;
-    if (N < 1 || (mode != 0 && mode != 1)) return MOP_EINVAL;
-    if (mode == 1 && !(fd_h > 0.0)) return MOP_EINVAL;
+    if (N < 1 || mode < 0 || mode > 2) return MOP_EINVAL;
+    if (mode != 0 && !(fd_h > 0.0)) return MOP_EINVAL;
     if (N > plan->max_beads) return MOP_ESIZE;
     hipStream_t st = plan->sys->ctx->stream;
     hipEvent_t ev[MOP_NPHASES + 1];
@@ -1136,7 +1137,7 @@ int mop_batch_workspace_size(mop_batch batch, size_t* bytes) {
 int mop_batch_veff_grad(mop_batch batch, const double* R, double* G, double* veff, int32_t mode,
                         double fd_h, void* ws) {
     if (!batch || !R || !G || !ws) return MOP_EINVAL;
-    if ((mode != 0 && mode != 1) || (mode == 1 && !(fd_h > 0.0))) return MOP_EINVAL;
+    if (mode < 0 || mode > 2 || (mode != 0 && !(fd_h > 0.0))) return MOP_EINVAL;
     CallPtrs cp = call_ptrs(ws);
     cp.R = R;
     cp.G = G;

@@ -197,6 +197,24 @@ def test_fd_mode_matches_oracle_fd(mop, ctx):
     assert e_fd < 1e-4
 
 
+@pytest.mark.parametrize("name,N", [("cfg1", 5), ("water300", 5)])
+def test_shared_bin_fd_matches_oracle_fd(name, N, mop, ctx):
+    """veff_grad mode 2 (finite differences on the binning of R) against the oracle's FD
+    gradient and against mode 1 (re-binned), at fd_h = the neighbour search margin."""
+    s = SMALL[name]()
+    h = 1e-4
+    R, _, _ = W.random_walk_path(s, N, 8, 0.005 if name == "cfg1" else None)
+    plan = mop.Plan(mop.System(ctx, s), N)
+    G2, v2 = mop.veff_grad(plan, cuda(R), mode=2, fd_h=h)
+    G1, v1 = mop.veff_grad(plan, cuda(R), mode=1, fd_h=h)
+    assert plan.status() == 0
+    Gofd = OP.veff_grad_fd(Model(s), R, h)
+    e2, e12 = rel(G2.cpu().numpy(), Gofd), rel(G2.cpu().numpy(), G1.cpu().numpy())
+    say(f"[fd shared-bin] {name}: vs oracle FD relL2 {e2:.2e}; vs re-binned FD {e12:.2e}")
+    assert e2 < 1e-4 and e12 < 1e-4
+    assert float(v1[0]) == float(v2[0])
+
+
 def test_batch_matches_single_paths(mop, ctx):
     specs = [(1002, 7, 31), (1503, 12, 32), (2001, 5, 33)]
     plans, paths, refs = [], [], []

@@ -117,17 +117,18 @@ def test_pme_veff_grad(name, N, mop, ctx):
     assert e3[0] == v
 
 
-def test_pme_fd_mode_matches_oracle_fd(mop, ctx):
+@pytest.mark.parametrize("mode", [1, 2])
+def test_pme_fd_mode_matches_oracle_fd(mode, mop, ctx):
     s = PME["water300"]()
     N, h = 5, 1e-4
     R, _, _ = W.random_walk_path(s, N, 8)
     plan = mop.Plan(mop.System(ctx, s), N)
-    Gfd, _ = mop.veff_grad(plan, cuda(R), mode=1, fd_h=h)
+    Gfd, _ = mop.veff_grad(plan, cuda(R), mode=mode, fd_h=h)
     assert plan.status() == 0
     m = Model(s)
     Gofd = OP.veff_grad_fd(m, R, h)
     e = rel(Gfd.cpu().numpy(), Gofd)
-    say(f"[pme fd] gpu-FD vs oracle-FD relL2 {e:.2e}")
+    say(f"[pme fd] mode {mode}: gpu-FD vs oracle-FD relL2 {e:.2e}")
     assert e < 1e-4
 
 
