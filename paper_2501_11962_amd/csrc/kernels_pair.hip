@@ -207,7 +207,7 @@ __device__ __forceinline__ void pair_term(const IAtom& I, const PairK& P, const 
 }
 
 template <int MODE, int PW, int N3, int EL>
-__global__ void __launch_bounds__(64 * PW) k_pair(const SegDev* __restrict__ segs, Launch L,
+__global__ void __launch_bounds__(64 * PW, EL == 1 ? 4 : 1) k_pair(const SegDev* __restrict__ segs, Launch L,
                                                  char* __restrict__ ws, int outsel, int energy_bead,
                                                  int lists) {
     using FL = Fields<MODE, N3>;
