@@ -301,3 +301,64 @@ def test_pme_cfg4_full_size_sampled(mop, ctx):
     e = rel(F.cpu().numpy()[0][idx], Fo)
     say(f"[pme cfg4] sampled bead_forces relL2 {e:.2e}")
     assert e < TOL_F
+    # the Hessian is symmetric at full size: u . H v = v . H u
+    rng = np.random.default_rng(8)
+    U = cuda(rng.normal(0.0, 1e-3, (1,) + R.shape[1:]))
+    V = cuda(rng.normal(0.0, 1e-3, (1,) + R.shape[1:]))
+    HV = mop.bead_hvp(plan, Rt[:1].contiguous(), V).double()
+    HU = mop.bead_hvp(plan, Rt[:1].contiguous(), U).double()
+    a, b = float((U * HV).sum()), float((V * HU).sum())
+    say(f"[pme cfg4] u.Hv {a:.9e}  v.Hu {b:.9e}")
+    assert abs(a - b) < 1e-5 * max(abs(a), abs(b))
+    assert plan.status() == 0
+
+
+def test_pme_edge_cases(mop, ctx):
+    """A single bead (V_eff = U(R^1), G = -F^1); one charged atom alone in the box (no
+    pairs: only its periodic images, the self term and the neutralising background); a
+    system with a net charge; coordinates shifted by whole box vectors."""
+    # single bead
+    s = PME["water300"]()
+    R = W.random_walk_path(s, 1, 3)[0]
+    plan = mop.Plan(mop.System(ctx, s), 1)
+    G, v = mop.veff_grad(plan, cuda(R))
+    m = Model(s)
+    Fo, Uo = m.forces(R[0]), m.energy(R[0])
+    e = rel(-G.cpu().numpy()[0], Fo)
+    say(f"[pme edge] N=1: G relL2 {e:.2e}")
+    assert e < TOL_F and abs(float(v[0]) - Uo) < TOL_V * (abs(Uo) + abs(m.e_const))
+    # one atom
+    s1 = W.with_pme(W.tiny(Q=1, charges=False, bonds=False))
+    s1["charge"] = np.array([0.7])
+    s1["x"] = np.array([[0.31, 0.77, 1.05]])
+    plan1 = mop.Plan(mop.System(ctx, s1), 2)
+    R1 = np.stack([s1["x"], s1["x"] + 0.01])
+    F1, U1 = mop.bead_forces(plan1, cuda(R1))
+    m1 = Model(s1)
+    for b in range(2):
+        Fo1, Uo1 = m1.forces(R1[b]), m1.energy(R1[b])
+        say(f"[pme edge] one atom, bead {b}: F {F1.cpu().numpy()[b]} vs {Fo1}, U {float(U1[b]):.9e} vs {Uo1:.9e}")
+        assert np.allclose(F1.cpu().numpy()[b], Fo1, rtol=1e-6, atol=1e-9)
+        assert float(U1[b]) == pytest.approx(Uo1, rel=1e-10)
+    # net charge
+    s2 = PME["tiny"]()
+    s2["charge"] = s2["charge"] + 0.05
+    R2 = W.random_walk_path(s2, 3, 4)[0]
+    plan2 = mop.Plan(mop.System(ctx, s2), 3)
+    F2, U2 = mop.bead_forces(plan2, cuda(R2))
+    m2 = Model(s2)
+    for b in range(3):
+        ef = rel(F2.cpu().numpy()[b], m2.forces(R2[b]))
+        Uo2 = m2.energy(R2[b])
+        assert ef < TOL_F and abs(float(U2[b]) - Uo2) < TOL_V * (abs(Uo2) + abs(m2.e_const))
+    # unwrapped coordinates
+    R3 = W.random_walk_path(s, 3, 5)[0]
+    shift = np.random.default_rng(2).integers(-3, 4, R3.shape) * s["box"]
+    plan3 = mop.Plan(mop.System(ctx, s), 3)
+    Ga, va = mop.veff_grad(plan3, cuda(R3))
+    Gb, vb = mop.veff_grad(plan3, cuda(R3 + shift))
+    e = rel(Gb.cpu().numpy(), Ga.cpu().numpy())
+    say(f"[pme edge] shifted by box vectors: G relL2 {e:.2e}")
+    assert e < 1e-7 and abs(float(va[0]) - float(vb[0])) < 1e-9 * abs(float(va[0]))
+    for p in (plan, plan1, plan2, plan3):
+        assert p.status() == 0
