@@ -100,9 +100,22 @@ def cpu_baseline(system, R, beads):
     t0 = time.perf_counter()
     Gsub, _ = OP.veff_grad(m, sub)
     dt = time.perf_counter() - t0
+    # one thread on a two-bead sample (one force and one Hessian-vector pass)
+    m1 = cl.CellModel(system, nthreads=1)
+    t1 = time.perf_counter()
+    OP.veff_grad(m1, np.ascontiguousarray(R[:2]))
+    dt1 = time.perf_counter() - t1
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next(l.split(":", 1)[1].strip() for l in f if l.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
     # beads 1 .. beads-1 of the sub-path carry the same gradient as in the whole path
     return dict(value=system["Q"] * beads / dt, unit="atom·beads/s", cores=cl.max_threads(),
-                kind="oracle",
+                kind="oracle", cpu_model=model, host_cpus=os.cpu_count(),
+                one_thread=dict(value=system["Q"] * 2 / dt1,
+                                sample=f"veff_grad of the first 2 beads, {dt1:.1f} s wall"),
                 sample=f"veff_grad of the first {beads} beads of the same path "
                        f"({beads - 1} force + {beads - 1} Hessian-vector passes over "
                        f"{system['Q']} atoms), {dt:.1f} s wall"), Gsub[:beads - 1]

@@ -126,13 +126,16 @@ int oracle_eval(const oracle_sys* s, const double* X, const double* V, double* F
     const int Q = s->Q;
     const double rc2 = s->rc * s->rc;
     double esum = 0.0;
+    int nt = 1;
 #ifdef _OPENMP
-    if (nthreads > 0) omp_set_num_threads(nthreads);
+    /* a per-call thread count (the OpenMP default is left unchanged) */
+    nt = nthreads > 0 ? nthreads : omp_get_max_threads();
 #endif
+    (void)nt;
     int lo[3], hi[3];
     for (int d = 0; d < 3; ++d) { lo[d] = c.n[d] >= 3 ? -1 : 0; hi[d] = c.n[d] >= 3 ? 1 : 0; }
 
-#pragma omp parallel for schedule(dynamic, 64) reduction(+ : esum)
+#pragma omp parallel for num_threads(nt) schedule(dynamic, 64) reduction(+ : esum)
     for (int i = 0; i < Q; ++i) {
         double fi[3] = {0, 0, 0}, hi_[3] = {0, 0, 0}, ei = 0.0;
         const int ci = c.cell[i];
