@@ -129,8 +129,8 @@ __device__ __forceinline__ void pair_term(const IAtom& I, const PairK& P, const 
     const float r2s = r2;
     const float rinv = __builtin_amdgcn_rsqf(r2s);
     const float rinv2 = rinv * rinv;
-    const float rinv6 = rinv2 * rinv2 * rinv2;
     const float rinv3 = rinv2 * rinv;
+    const float rinv6 = rinv3 * rinv3;
     const float4 T = tabrow[tj];
     const float qq = I.q * qj;
     const float C1 = fmaf(qq, P.crf1, T.z);
@@ -178,12 +178,15 @@ __device__ __forceinline__ void pair_term(const IAtom& I, const PairK& P, const 
         }
     } else {
         const float h6 = fmaf(T.w, rinv6, G6);
-        float h = h6 * (rinv8 * (-8.0f * rinv2));
+        float h;
         if (EL == 0) {
-            h = fmaf(3.0f * qq, rinv3 * rinv2, h);
-            h = fmaf(-C1, rinv3, h);
+            // h = r^-5 (3 qq - 8 h6 r^-5) - C1 r^-3
+            const float rinv5 = rinv3 * rinv2;
+            h = fmaf(h6 * rinv5, -8.0f, 3.0f * qq);
+            h = fmaf(rinv5, h, -(C1 * rinv3));
             h = in ? h : 0.0f;
         } else {
+            h = h6 * (rinv8 * (-8.0f * rinv2));
             const float he = fmaf(P.b2x2, D, 3.0f * fmaf(D, rinv2, E * rinv3)) * rinv2;
             h = fmaf(-C1, rinv3, h);
             h = in ? fmaf(qq, he, h) : (cor ? qq * he : 0.0f);
