@@ -93,14 +93,20 @@ struct IAtom {
 
 struct PairK {
     float sx, sy, sz, rc2, krf2, crf1, krf, crf, e0rf, beta, c2b, b2x2;
+    float krf2_3, crf1_3;  // krf2 / 3, crf1 / 3 (Hessian kernel: charges carried as 3 q_j)
 };
+
+// The reaction-field Hessian kernel keeps 3 q_j in its ring, so that the 3 qq of h needs no
+// multiply; g and C1 then use constants divided by 3.
+template <int MODE, int N3, int EL>
+constexpr bool THREE_Q = MODE == 1 && N3 == 0 && EL == 0;
 
 // One pair term for lane atom I and j-atom (jx, jy, jz): coordinates relative to the
 // box centre, or (EX) raw fixed-point bits.  The contribution to atom i (force: g d;
 // HVP: g (v_i - v_j) + h (d . (v_i - v_j)) d) is added to (ax, ay, az) with fused
 // multiply-adds; with T_OUT it is also returned in t (for the j side).  tabrow points
 // at the type-table row of atom i.
-template <int MODE, bool EX, bool WANTE, bool T_OUT, int EL>
+template <int MODE, bool EX, bool WANTE, bool T_OUT, int EL, bool Q3 = false>
 __device__ __forceinline__ void pair_term(const IAtom& I, const PairK& P, const float4* tabrow,
                                           int ntab,
                                           float jx, float jy, float jz,
@@ -132,14 +138,14 @@ __device__ __forceinline__ void pair_term(const IAtom& I, const PairK& P, const 
     const float rinv3 = rinv2 * rinv;
     const float rinv6 = rinv3 * rinv3;
     const float4 T = tabrow[tj];
-    const float qq = I.q * qj;
-    const float C1 = fmaf(qq, P.crf1, T.z);
+    const float qq = I.q * qj;  // 3 q_i q_j when Q3
+    const float C1 = fmaf(qq, Q3 ? P.crf1_3 : P.crf1, T.z);
     const float G6 = fmaf(T.x, rinv6, T.y);
     const float rinv8 = rinv6 * rinv2;
     float g, E = 0.0f, D = 0.0f, r = 0.0f;
     if (EL == 0) {
         g = G6 * rinv8;
-        g = fmaf(qq, P.krf2 - rinv3, g);
+        g = fmaf(qq, Q3 ? fmaf(rinv3, -1.0f / 3.0f, P.krf2_3) : P.krf2 - rinv3, g);
         g = fmaf(C1, rinv, g);
         g = in ? g : 0.0f;
     } else {
@@ -182,7 +188,7 @@ __device__ __forceinline__ void pair_term(const IAtom& I, const PairK& P, const 
         if (EL == 0) {
             // h = r^-5 (3 qq - 8 h6 r^-5) - C1 r^-3
             const float rinv5 = rinv3 * rinv2;
-            h = fmaf(h6 * rinv5, -8.0f, 3.0f * qq);
+            h = fmaf(h6 * rinv5, -8.0f, Q3 ? qq : 3.0f * qq);
             h = fmaf(rinv5, h, -(C1 * rinv3));
             h = in ? h : 0.0f;
         } else {
@@ -272,6 +278,9 @@ __global__ void __launch_bounds__(64 * PW, EL == 1 ? 4 : 1) k_pair(const SegDev*
     P.beta = sg->s.ew_beta;
     P.c2b = sg->s.ew_c2b;
     P.b2x2 = sg->s.ew_b2x2;
+    P.krf2_3 = sg->s.krf2 * (1.0f / 3.0f);
+    P.crf1_3 = sg->s.crf1 * (1.0f / 3.0f);
+    constexpr float QSC = THREE_Q<MODE, N3, EL> ? 3.0f : 1.0f;
     const float sx = P.sx, sy = P.sy, sz = P.sz;
     const float rcs = sg->s.rcs, rcs2 = sg->s.rcs2;
 
@@ -484,7 +493,7 @@ __global__ void __launch_bounds__(64 * PW, EL == 1 ? 4 : 1) k_pair(const SegDev*
                 }
             }
             float tx, ty, tz, en = 0.f;
-            pair_term<MODE, EX, WE, N3 == 1, EL>(I, P, tabrow, ntab, jxv, jyv, jzv, qjv, kj, tjv, vjx, vjy,
+            pair_term<MODE, EX, WE, N3 == 1, EL, THREE_Q<MODE, N3, EL>>(I, P, tabrow, ntab, jxv, jyv, jzv, qjv, kj, tjv, vjx, vjy,
                                              vjz, valid, ax, ay, az, tx, ty, tz, en);
             if (WE) eacc += N3 ? en : 0.5f * en;
             if (N3) {
@@ -574,7 +583,7 @@ __global__ void __launch_bounds__(64 * PW, EL == 1 ? 4 : 1) k_pair(const SegDev*
                 re[F_X * RING] = jx;
                 re[F_Y * RING] = jy;
                 re[F_Z * RING] = jz;
-                re[F_Q * RING] = jq;
+                re[F_Q * RING] = QSC * jq;
                 re[F_K * RING] = __int_as_float(jk);
                 re[F_T * RING] = __int_as_float(jt);
                 if (N3) {
@@ -632,7 +641,7 @@ __global__ void __launch_bounds__(64 * PW, EL == 1 ? 4 : 1) k_pair(const SegDev*
                 re[F_X * RING] = jx;
                 re[F_Y * RING] = jy;
                 re[F_Z * RING] = jz;
-                re[F_Q * RING] = __uint_as_float(uj.w);
+                re[F_Q * RING] = QSC * __uint_as_float(uj.w);
                 re[F_K * RING] = __int_as_float(mj.x);
                 re[F_T * RING] = __int_as_float(mj.y);
                 re[FV * RING] = jv.x;
