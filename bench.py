@@ -34,6 +34,11 @@ PEAK_HBM_GBS = 8000.0
 # counted from the pair formulas with Newton's third law (each pair once).
 FLOP_FORCE_PAIR = 34
 FLOP_HVP_PAIR = 60
+# Ewald real space: the reaction-field terms of g (and h) replaced by erfc/exp terms
+# (erfc as exp(-x^2) times a degree-8 polynomial in 1/(1 + x/2); exp and reciprocal 1 each):
+# g 11 -> 38 flops, h 11 -> 16 flops.
+FLOP_FORCE_PAIR_EWALD = 61
+FLOP_HVP_PAIR_EWALD = 92
 FD_SWEEP = (1e-5, 3e-5, 1e-4, 3e-4, 1e-3)   # FD displacement lengths h (nm)
 PAIR_SRC = os.path.join(ROOT, "paper_2501_11962_amd", "csrc", "kernels_pair.hip")
 
@@ -244,7 +249,7 @@ def bench_pmd(args, mop, ctx, plan, system, Rt, ms_grad, log):
     return out
 
 
-def bench_pme(args, mop, ctx, system, R, ms_rf, log):
+def bench_pme(args, mop, ctx, system, R, ms_rf, npairs, log):
     """The same path with particle-mesh Ewald electrostatics, the paper's own setting
     (Appendix A.1): Ewald real-space pair kernels at the same cut-off, B-spline order 4
     on a grid of at most 0.12 nm per point, rocFFT in FP64.  Reports ms per veff_grad
@@ -293,12 +298,23 @@ def bench_pme(args, mop, ctx, system, R, ms_rf, log):
         acc = ph if acc is None else {k: acc[k] + ph[k] for k in acc}
     n = max(args.steps // 2, 3)
     phases = {k: acc[k] / n for k in acc}
+    pair_beads = N - 1
+    t_hvp, t_force = phases["hvp"] * 1e-3, phases["force"] * 1e-3
+    ach = FLOP_HVP_PAIR_EWALD * npairs * pair_beads / t_hvp / 1e12
+    roof = dict(bound="alu", kernel="k_pair<1,4,0,1> (Ewald pair Hessian-vector product)",
+                achieved=round(ach, 3), peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
+                frac=round(ach / PEAK_FP32_TFLOPS, 4), launch_ms=round(phases["hvp"], 4),
+                force_kernel=dict(achieved=round(FLOP_FORCE_PAIR_EWALD * npairs * pair_beads
+                                                 / t_force / 1e12, 3),
+                                  launch_ms=round(phases["force"], 4)),
+                mesh_ms=dict(force=round(phases["pme_force"], 4), hvp=round(phases["pme_hvp"], 4)))
     out = dict(workload=f"{system['name']} with particle-mesh Ewald: grid {grid[0]}x{grid[1]}x"
                         f"{grid[2]}, order {s['pme_order']}, beta {beta:.4f} / nm, "
                         f"real-space cut-off {s['rc']} nm",
                ms_per_step=ms, ms_eager=ms_eager, ms_graph=ms_graph,
                value=Q * N / (ms * 1e-3), unit="atom·beads/s",
-               cost_vs_reaction_field=ms / ms_rf, phases_ms=phases, device_status=st,
+               cost_vs_reaction_field=ms / ms_rf, phases_ms=phases, roofline=roof,
+               device_status=st,
                veff_finite=bool(torch.isfinite(v).all()))
     log(f"[bench] PME: {ms:.3f} ms/step (eager {ms_eager:.3f}, graph {ms_graph}), "
         f"phases {json.dumps({k: round(x, 3) for k, x in phases.items()})}, status {st}")
@@ -500,7 +516,7 @@ def main():
     if not args.no_batch:
         out["batch"] = bench_batch(args, mop, ctx, log)
     if not args.no_pme:
-        out["pme"] = bench_pme(args, mop, ctx, system, R, ms, log)
+        out["pme"] = bench_pme(args, mop, ctx, system, R, ms, npairs, log)
     print(json.dumps(out), flush=True)
 
 

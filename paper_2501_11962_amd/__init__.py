@@ -77,7 +77,7 @@ EXPORTS = [
     "veff_grad_timed", "pmd_step", "mop_bias_create", "mop_bias_destroy", "mop_bias_reset",
     "mop_bias_apply", "mop_bias_history", "mop_system_pme_info",
 ]
-PHASES = ["bin", "force", "resid", "hvp", "fd", "assemble"]
+PHASES = ["bin", "force", "pme_force", "resid", "hvp", "pme_hvp", "fd", "assemble"]
 
 
 def lib():

@@ -844,10 +844,11 @@ static void path_sequence(const SegDev* dsegs, const SegDev* hsegs, const Launch
     // exact gradients: the force pass records neighbour lists for the Hessian pass
     const int lists = (grad && mode == 0) ? 1 : 0;
     run_pair(dsegs, hsegs, base, cp.ws, 0, 0, 0, waves, n3, st, lists);
-    if (pme) pme_forces(pl, base.nb[0], cp, 0, 0, true, st);
     mark(2);
-    run_resid(dsegs, hsegs, base, cp, st);
+    if (pme) pme_forces(pl, base.nb[0], cp, 0, 0, true, st);
     mark(3);
+    run_resid(dsegs, hsegs, base, cp, st);
+    mark(4);
     if (grad) {
         Launch Lh = base;
         bool any = false;
@@ -855,11 +856,11 @@ static void path_sequence(const SegDev* dsegs, const SegDev* hsegs, const Launch
             Lh.nb[p] = base.N[p] - 1;
             any = any || Lh.nb[p] > 0;
         }
-        if (any && mode == 0) {
-            run_pair(dsegs, hsegs, Lh, cp.ws, 1, 0, -1, waves, n3, st, 2 * lists);
-            if (pme) pme_hvp(pl, Lh.nb[0], cp, wsp_host<double>(cp.ws, hsegs[0].o_d64), st);
-        }
-        mark(4);
+        if (any && mode == 0) run_pair(dsegs, hsegs, Lh, cp.ws, 1, 0, -1, waves, n3, st, 2 * lists);
+        mark(5);
+        if (any && mode == 0 && pme)
+            pme_hvp(pl, Lh.nb[0], cp, wsp_host<double>(cp.ws, hsegs[0].o_d64), st);
+        mark(6);
         if (any && mode != 0) {
             // mode 1 re-bins each displaced configuration; mode 2 keeps R's binning
             for (int sgn : {+1, -1}) {
@@ -869,14 +870,15 @@ static void path_sequence(const SegDev* dsegs, const SegDev* hsegs, const Launch
                 if (pme) pme_forces(pl, Lh.nb[0], cp, sgn, sgn > 0 ? 1 : 2, true, st);
             }
         }
-        mark(5);
+        mark(7);
         run_assemble(dsegs, hsegs, base, cp, mode != 0 ? 1 : 0, st);
     } else {
-        mark(4);
         mark(5);
+        mark(6);
+        mark(7);
     }
     run_reduce_veff(dsegs, hsegs, base, cp, st);
-    mark(6);
+    mark(8);
 }
 
 int veff_energy(mop_plan plan, const double* R, int32_t N, double* veff, double* u1,
