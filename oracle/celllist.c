@@ -5,7 +5,10 @@
  * library (which shares no code with this file).
  *
  * Same definitions as oracle/potential.py (shifted-force Lennard-Jones + reaction
- * field, harmonic bonds, 1-2/1-3 exclusions; the system of section 1.1, eq. 1):
+ * field, harmonic bonds, 1-2/1-3 exclusions; the system of section 1.1, eq. 1).  With
+ * ewald set, the reaction field is replaced by the Ewald real-space term
+ * qq erfc(beta r)/r (shifted-force) and excluded pairs within r_c carry
+ * -qq erf(beta r)/r; the reciprocal part is added by the Python wrapper (pme.py).
  *   pair separation d = x_j - x_i (minimum image), r = |d|
  *   g = phi_sf'(r)/r, h = (phi''(r) - phi_sf'(r)/r)/r^2
  *   F_i += g d;  (H v)_i += g (v_i - v_j) + h (d . (v_i - v_j)) d
@@ -39,7 +42,11 @@ typedef struct {
     const int* bonds;     /* [nbonds*2] */
     const double* r0;     /* [nbonds] */
     const double* kb;     /* [nbonds] */
+    int ewald;            /* 1: Ewald real space instead of the reaction field */
+    double beta;          /* Ewald splitting parameter (nm^-1) */
 } oracle_sys;
+
+static const double PI_D = 3.14159265358979323846;
 
 static double mi(double d, double L) { return d - L * nearbyint(d / L); }
 
@@ -49,30 +56,51 @@ static int is_excluded(const oracle_sys* s, int i, int j) {
     return 0;
 }
 
-/* Shifted-force LJ + RF: returns phi_sf(r); writes phi_sf'(r) and phi''(r). */
+/* Electrostatic pair energy (reaction field, or Ewald real space qq erfc(beta r)/r) and
+ * its first and second derivatives. */
+static double elec_terms(const oracle_sys* s, double qq, double r, double* d1, double* d2) {
+    double ir = 1.0 / r;
+    if (!s->ewald) {
+        *d1 = qq * (-ir * ir + 2.0 * s->krf * r);
+        *d2 = qq * (2.0 * ir * ir * ir + 2.0 * s->krf);
+        return qq * (ir + s->krf * r * r - s->crf);
+    }
+    double br = s->beta * r, E = erfc(br);
+    double D = 2.0 * s->beta / sqrt(PI_D) * exp(-br * br);
+    *d1 = qq * (-E * ir * ir - D * ir);
+    *d2 = qq * (2.0 * E * ir * ir * ir + D * (2.0 * ir * ir + 2.0 * s->beta * s->beta));
+    return qq * E * ir;
+}
+
+/* Ewald correction of an excluded pair: -qq erf(beta r)/r and its derivatives. */
+static double excl_terms(const oracle_sys* s, double qq, double r, double* d1, double* d2) {
+    double ir = 1.0 / r, br = s->beta * r, A = erf(br);
+    double D = 2.0 * s->beta / sqrt(PI_D) * exp(-br * br);
+    *d1 = -qq * (D * ir - A * ir * ir);
+    *d2 = -qq * (-2.0 * s->beta * s->beta * D - 2.0 * D * ir * ir + 2.0 * A * ir * ir * ir);
+    return -qq * A * ir;
+}
+
+/* Shifted-force LJ + electrostatics: returns phi_sf(r); writes phi_sf'(r) and phi''(r). */
 static double pair_terms(const oracle_sys* s, int ti, int tj, double qq, double r,
                          double* d1_out, double* d2_out) {
     const double c6 = s->c6[ti * s->ntypes + tj], c12 = s->c12[ti * s->ntypes + tj];
-    const double rc = s->rc, krf = s->krf, crf = s->crf;
+    const double rc = s->rc;
     /* Lennard-Jones */
     double ir = 1.0 / r, ir6 = pow(ir, 6.0), ir12 = ir6 * ir6;
     double lj = c12 * ir12 - c6 * ir6;
     double lj1 = (-12.0 * c12 * ir12 + 6.0 * c6 * ir6) * ir;
     double lj2 = (156.0 * c12 * ir12 - 42.0 * c6 * ir6) * ir * ir;
-    /* reaction field */
-    double rf = qq * (ir + krf * r * r - crf);
-    double rf1 = qq * (-ir * ir + 2.0 * krf * r);
-    double rf2 = qq * (2.0 * ir * ir * ir + 2.0 * krf);
+    double el1, el2, el = elec_terms(s, qq, r, &el1, &el2);
     /* values at the cutoff */
     double irc = 1.0 / rc, irc6 = pow(irc, 6.0), irc12 = irc6 * irc6;
     double ljc = c12 * irc12 - c6 * irc6;
     double ljc1 = (-12.0 * c12 * irc12 + 6.0 * c6 * irc6) * irc;
-    double rfc = qq * (irc + krf * rc * rc - crf);
-    double rfc1 = qq * (-irc * irc + 2.0 * krf * rc);
-    double phic = ljc + rfc, d1c = ljc1 + rfc1;
-    *d1_out = lj1 + rf1 - d1c;
-    *d2_out = lj2 + rf2;
-    return lj + rf - phic - (r - rc) * d1c;
+    double elc1, elc2, elc = elec_terms(s, qq, rc, &elc1, &elc2);
+    double phic = ljc + elc, d1c = ljc1 + elc1;
+    *d1_out = lj1 + el1 - d1c;
+    *d2_out = lj2 + el2;
+    return lj + el - phic - (r - rc) * d1c;
 }
 
 typedef struct {
@@ -154,10 +182,12 @@ int oracle_eval(const oracle_sys* s, const double* X, const double* V, double* F
                         for (int e = 0; e < 3; ++e) d[e] = mi(X[3 * j + e] - X[3 * i + e], s->box[e]);
                         double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
                         if (r2 >= rc2) continue;
-                        if (is_excluded(s, i, j)) continue;
+                        const int ex = is_excluded(s, i, j);
+                        if (ex && !s->ewald) continue;
                         double r = sqrt(r2), d1, d2;
                         double qq = s->fq * s->q[i] * s->q[j];
-                        double phi = pair_terms(s, s->type[i], s->type[j], qq, r, &d1, &d2);
+                        double phi = ex ? excl_terms(s, qq, r, &d1, &d2)
+                                        : pair_terms(s, s->type[i], s->type[j], qq, r, &d1, &d2);
                         double g = d1 / r;
                         ei += 0.5 * phi;
                         for (int e = 0; e < 3; ++e) fi[e] += g * d[e];

@@ -39,6 +39,7 @@ class _Sys(C.Structure):
         ("excl_start", C.POINTER(C.c_int)), ("excl", C.POINTER(C.c_int)),
         ("nbonds", C.c_int), ("bonds", C.POINTER(C.c_int)),
         ("r0", C.POINTER(C.c_double)), ("kb", C.POINTER(C.c_double)),
+        ("ewald", C.c_int), ("beta", C.c_double),
     ]
 
 
@@ -61,13 +62,11 @@ def _ptr(a, ct):
 
 
 class CellModel(Model):
-    """Model whose energy / forces / hvp run in celllist.c."""
+    """Model whose energy / forces / hvp run in celllist.c (pair terms and bonds); for PME
+    systems the reciprocal part and the constant terms come from pme.py as in Model."""
 
     def __init__(self, system, nthreads=0):
         super().__init__(system)
-        if self.elec != "rf":
-            raise NotImplementedError("the C cell-list oracle covers reaction-field "
-                                      "electrostatics only; use potential.Model for PME")
         self.nthreads = int(nthreads)
         Q = self.Q
         ex = self.excluded
@@ -105,6 +104,8 @@ class CellModel(Model):
         s.nbonds = int(len(self.bonds))
         s.bonds = _ptr(self._bonds, C.c_int)
         s.r0, s.kb = _ptr(self._r0, C.c_double), _ptr(self._kb, C.c_double)
+        s.ewald = 1 if self.pme is not None else 0
+        s.beta = self.beta if self.pme is not None else 0.0
         self._s = s
 
     def eval(self, X, V=None, forces=True, energy=True):
@@ -119,7 +120,15 @@ class CellModel(Model):
                         F.ctypes.data if F is not None else None,
                         HV.ctypes.data if HV is not None else None,
                         C.byref(u) if energy else None, self.nthreads)
-        return u.value, F, HV
+        e = u.value
+        if self.pme is not None:
+            if energy:
+                e += self.pme.energy(X) + self.e_const
+            if F is not None:
+                F += self.pme.forces(X)
+            if HV is not None:
+                HV += self.pme.hvp(X, Vc)
+        return e, F, HV
 
     def energy(self, X):
         return self.eval(X, forces=False)[0]

@@ -214,3 +214,18 @@ def test_with_pme_grid_sizes():
             while m % f == 0:
                 m //= f
         assert m == 1
+
+
+@pytest.mark.parametrize("name", ["tiny", "water300"])
+def test_cell_list_oracle_matches_brute_force_with_pme(name):
+    """The C cell-list oracle (Ewald real space and exclusion corrections in C, the mesh
+    part from pme.py) equals the numpy brute force for PME systems."""
+    from oracle import cl
+    base = W.tiny(Q=24, seed=5) if name == "tiny" else W.water_box(300, seed=5, rc=0.6)
+    s = W.with_pme(base)
+    m, c = Model(s), cl.CellModel(s)
+    X = s["x"]
+    V = np.random.default_rng(1).normal(size=X.shape)
+    assert c.energy(X) == pytest.approx(m.energy(X), rel=1e-12)
+    assert np.max(np.abs(c.forces(X) - m.forces(X))) < 1e-12 * np.max(np.abs(m.forces(X)))
+    assert np.max(np.abs(c.hvp(X, V) - m.hvp(X, V))) < 1e-12 * np.max(np.abs(m.hvp(X, V)))
