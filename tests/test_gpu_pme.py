@@ -285,22 +285,36 @@ def _sampled_forces(m, X, idx):
     return F + m.pme.forces(X)[idx]
 
 
-def test_pme_cfg4_full_size_sampled(mop, ctx):
-    """The 150,000-atom membrane-shaped workload with PME (grid at 0.12 nm): forces of
-    bead 1 through bead_forces on 48 sampled atoms, and the finiteness of veff_grad over
-    all 16 beads in the benchmark's launch configuration."""
+def test_pme_cfg4_full_size(mop, ctx):
+    """The 150,000-atom membrane-shaped workload with PME (grid at 0.12 nm) in the
+    benchmark's launch configuration: the gradient of beads 1 and 16 and the forces of
+    bead 1 against the FP64 cell-list oracle (Ewald real space in C, mesh in numpy);
+    48 sampled atoms' forces against the brute-force per-atom sum as well."""
+    from oracle import cl
     s = W.with_pme(W.cfg4())
     R, _, _ = W.random_walk_path(s, 16, 402)
-    plan = mop.Plan(mop.System(ctx, s), 16)
+    N = R.shape[0]
+    plan = mop.Plan(mop.System(ctx, s), N)
     Rt = cuda(R)
     G, v = mop.veff_grad(plan, Rt)
+    G = G.cpu().numpy()
     assert plan.status() == 0 and np.isfinite(float(v[0]))
+    m = cl.CellModel(s)
+    c, K = OP.coefficients(m)
+    F0, FN = m.forces(R[0]), m.forces(R[N - 2])
+    d0 = min_image(R[1] - R[0], m.box) - c[:, None] * F0
+    dN = min_image(R[N - 1] - R[N - 2], m.box) - c[:, None] * FN
+    G1 = -F0 - K[:, None] * d0 + 0.5 * m.hvp(R[0], d0)
+    e1, eN = rel(G[0], G1), rel(G[N - 1], K[:, None] * dN)
+    say(f"[pme cfg4] G relL2 bead 1 {e1:.2e}, bead N {eN:.2e}")
+    assert e1 < TOL_G and eN < TOL_G
     F, _ = mop.bead_forces(plan, Rt[:1].contiguous(), want_energy=False)
+    F = F.cpu().numpy()[0]
+    ef = rel(F, F0)
     idx = np.random.default_rng(7).choice(s["Q"], 48, replace=False)
-    Fo = _sampled_forces(Model(s), R[0], idx)
-    e = rel(F.cpu().numpy()[0][idx], Fo)
-    say(f"[pme cfg4] sampled bead_forces relL2 {e:.2e}")
-    assert e < TOL_F
+    es = rel(F[idx], _sampled_forces(Model(s), R[0], idx))
+    say(f"[pme cfg4] bead_forces relL2 {ef:.2e} (48 sampled atoms, brute force: {es:.2e})")
+    assert ef < TOL_F and es < TOL_F
     # the Hessian is symmetric at full size: u . H v = v . H u
     rng = np.random.default_rng(8)
     U = cuda(rng.normal(0.0, 1e-3, (1,) + R.shape[1:]))
