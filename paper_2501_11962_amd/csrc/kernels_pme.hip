@@ -158,17 +158,40 @@ __global__ void __launch_bounds__(EWB) k_pme_tile_count(const SegDev* __restrict
     const SysDev& s = sg.s;
     const int b = blockIdx.x / sg.bpb;
     const int i = (blockIdx.x - b * sg.bpb) * EWB + threadIdx.x;
-    if (b >= nb || i >= s.Q) return;
-    double x[3], w[3];
-    atom_pos(sg, ws, R, b, i, fdsign, fdh, x);
-    int bse[3];
-    grid_base(s, x, bse, w);
-    const int tile = (s.tile_of[s.tof_off[0] + bse[0]] * s.ntl[1] + s.tile_of[s.tof_off[1] + bse[1]]) *
-                         s.ntl[2] +
-                     s.tile_of[s.tof_off[2] + bse[2]];
-    const int rank = atomicAdd(wsp<int>(ws, sg.o_ptc) + (size_t)b * s.ntile + tile, 1);
-    wsp<int>(ws, sg.o_ptid)[(size_t)b * s.Q + i] = tile;
-    wsp<int>(ws, sg.o_ptrk)[(size_t)b * s.Q + i] = rank;
+    if (b >= nb) return;
+    const bool valid = i < s.Q;
+    int tile = -1;
+    if (valid) {
+        double x[3], w[3];
+        atom_pos(sg, ws, R, b, i, fdsign, fdh, x);
+        int bse[3];
+        grid_base(s, x, bse, w);
+        tile = (s.tile_of[s.tof_off[0] + bse[0]] * s.ntl[1] + s.tile_of[s.tof_off[1] + bse[1]]) *
+                   s.ntl[2] +
+               s.tile_of[s.tof_off[2] + bse[2]];
+    }
+    // Neighbouring atoms mostly share a tile: one atomic per distinct tile of the wave,
+    // ranks in lane order inside it.
+    int* cnt = wsp<int>(ws, sg.o_ptc) + (size_t)b * s.ntile;
+    const int lane = threadIdx.x & 63;
+    unsigned long long todo = __ballot(valid);
+    int rank = 0;
+    while (todo) {
+        const int leader = __ffsll((long long)todo) - 1;
+        const int lt = __shfl(tile, leader, 64);
+        const unsigned long long same = __ballot(tile == lt) & todo;
+        int base = 0;
+        if (lane == leader) base = atomicAdd(cnt + lt, (int)__popcll(same));
+        base = __shfl(base, leader, 64);
+        if (tile == lt)
+            rank = base + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(same >> 32),
+                                                         __builtin_amdgcn_mbcnt_lo((unsigned)same, 0u));
+        todo &= ~same;
+    }
+    if (valid) {
+        wsp<int>(ws, sg.o_ptid)[(size_t)b * s.Q + i] = tile;
+        wsp<int>(ws, sg.o_ptrk)[(size_t)b * s.Q + i] = rank;
+    }
 }
 
 __global__ void __launch_bounds__(PME_BLOCK) k_pme_tile_zero(const SegDev* __restrict__ segs,
