@@ -246,6 +246,27 @@ def bench_pmd(args, mop, ctx, plan, system, Rt, ms_grad, log):
                energies_finite=bool(torch.isfinite(E).all()))
     log(f"[bench] pmd: {ms:.3f} ms/step (veff_grad {ms_grad:.3f}), status {st}")
     plan.clear_status()
+    if not args.no_cpu_baseline:
+        # CPU baseline: one biased Langevin step of the FP64 oracle (cell list, all host
+        # threads) on the first two beads of the path
+        from oracle import cl
+        from oracle import mop_bias as MB
+        from oracle import path as OP
+        from oracle import pmd
+        m = cl.CellModel(system)
+        R2 = np.ascontiguousarray(Rt[:2].cpu().numpy())
+        ob = MB.Bias(A, B, system["mass"], system["box"], 0.02, 1.0, 10.0, kT, stride=5)
+        G2, _ = OP.veff_grad(m, R2)
+        G2 = G2 + ob.apply(R2, 0)[2]
+        t0 = time.perf_counter()
+        pmd.baoab_step(m, R2, np.zeros_like(R2), G2, system["mass"], tau, 250.0, kT, 7, 1, ob)
+        dt = time.perf_counter() - t0
+        Qs = system["Q"]
+        out["cpu_baseline"] = dict(value=Qs * 2 / dt, unit="atom·beads/s", cores=cl.max_threads(),
+                                   kind="oracle",
+                                   sample=f"one biased Langevin step of a 2-bead path "
+                                          f"({Qs} atoms), {dt:.1f} s wall")
+        log(f"[bench] pmd CPU oracle: {Qs * 2 / dt:.3e} atom*beads/s")
     return out
 
 
