@@ -62,6 +62,7 @@ struct mop_plan_s {
     SegDev* dseg;
     size_t ws_bytes;
     PmeFft fft;           // PME systems
+    mutable bool fft_failed = false;  // a transform could not be enqueued (reported by the call)
 };
 
 struct mop_bias_s {
@@ -654,12 +655,16 @@ static int make_fft(PmeFft& f, const int K[3], int batch) {
 }
 
 // One batched transform on `st` (the work buffer lives in the caller's workspace).
-static void run_fft(const PmeFft& f, bool forward, void* in, void* out, void* work, hipStream_t st) {
-    (void)rocfft_execution_info_set_stream(f.info, st);
-    if (f.work) (void)rocfft_execution_info_set_work_buffer(f.info, work, f.work);
+static void run_fft(const mop_plan_s* pl, bool forward, void* in, void* out, void* work,
+                    hipStream_t st) {
+    const PmeFft& f = pl->fft;
+    bool ok = rocfft_execution_info_set_stream(f.info, st) == rocfft_status_success;
+    if (f.work)
+        ok = ok && rocfft_execution_info_set_work_buffer(f.info, work, f.work) == rocfft_status_success;
     void* ib[1] = {in};
     void* ob[1] = {out};
-    (void)rocfft_execute(forward ? f.fwd : f.bwd, ib, ob, f.info);
+    ok = ok && rocfft_execute(forward ? f.fwd : f.bwd, ib, ob, f.info) == rocfft_status_success;
+    if (!ok) pl->fft_failed = true;
 }
 
 int mop_plan_create(mop_system sys, int32_t max_beads, const mop_plan_opts* opts, mop_plan* out) {
@@ -757,6 +762,16 @@ static int finish(mop_ctx ctx) {
     return hipGetLastError() == hipSuccess ? MOP_OK : MOP_EHIP;
 }
 
+// finish() plus the plan's transform errors (PME), which are cleared once reported.
+static int finish_plan(mop_plan plan) {
+    int rc = finish(plan->sys->ctx);
+    if (plan->fft_failed) {
+        plan->fft_failed = false;
+        rc = MOP_EHIP;
+    }
+    return rc;
+}
+
 // PME reciprocal forces of nb pair beads at R (displaced by fdsign eps d), added to the
 // float4 output outsel (when gather); the potential goes to pphi for the undisplaced
 // configuration (kept for the Hessian pass), else to pgr.  Energy partials are formed
@@ -767,9 +782,9 @@ static void pme_forces(const mop_plan_s* pl, int nb, const CallPtrs& cp, int fds
     char* ws = cp.ws;
     run_pme_sort(pl->dseg, h, nb, ws, cp.R, fdsign, cp.fd_h, st);
     run_pme_spread(pl->dseg, h, nb, h.maxb, ws, cp.R, nullptr, 0, fdsign, cp.fd_h, st);
-    run_fft(pl->fft, true, ws + h.o_pgr, ws + h.o_pgc, ws + h.o_pfw, st);
+    run_fft(pl, true, ws + h.o_pgr, ws + h.o_pgc, ws + h.o_pfw, st);
     run_pme_solve(pl->dseg, h, nb, ws, fdsign == 0 ? 1 : 0, st);
-    run_fft(pl->fft, false, ws + h.o_pgc, ws + (fdsign == 0 ? h.o_pphi : h.o_pgr), ws + h.o_pfw, st);
+    run_fft(pl, false, ws + h.o_pgc, ws + (fdsign == 0 ? h.o_pphi : h.o_pgr), ws + h.o_pfw, st);
     if (gather)
         run_pme_gather(pl->dseg, h, nb, ws, cp.R, nullptr, 0, fdsign, cp.fd_h, outsel,
                        fdsign != 0 ? 1 : 0, st);
@@ -782,9 +797,9 @@ static void pme_hvp(const mop_plan_s* pl, int nb, const CallPtrs& cp, const doub
     const SegDev& h = pl->hseg;
     char* ws = cp.ws;
     run_pme_spread(pl->dseg, h, nb, h.maxb, ws, cp.R, V, 1, 0, 0.0, st);
-    run_fft(pl->fft, true, ws + h.o_pgr, ws + h.o_pgc, ws + h.o_pfw, st);
+    run_fft(pl, true, ws + h.o_pgr, ws + h.o_pgc, ws + h.o_pfw, st);
     run_pme_solve(pl->dseg, h, nb, ws, 0, st);
-    run_fft(pl->fft, false, ws + h.o_pgc, ws + h.o_pgr, ws + h.o_pfw, st);
+    run_fft(pl, false, ws + h.o_pgc, ws + h.o_pgr, ws + h.o_pfw, st);
     run_pme_gather(pl->dseg, h, nb, ws, cp.R, V, 1, 0, 0.0, 1, 0, st);
 }
 
@@ -802,7 +817,7 @@ int bead_forces(mop_plan plan, const double* R, int32_t B, float* F, double* U, 
     run_pair(plan->dseg, &plan->hseg, L, cp.ws, 0, 0, U ? -2 : -1, plan->waves, plan->newton3, st);
     if (plan->hseg.s.elec == 1) pme_forces(plan, B, cp, 0, 0, true, st);
     run_finalize_forces(plan->dseg, &plan->hseg, L, cp, st);
-    return finish(plan->sys->ctx);
+    return finish_plan(plan);
 }
 
 int bead_hvp(mop_plan plan, const double* R, const double* V, int32_t B, float* HV, void* ws) {
@@ -824,7 +839,7 @@ int bead_hvp(mop_plan plan, const double* R, const double* V, int32_t B, float* 
         pme_hvp(plan, B, cp, V, st);
     }
     run_finalize_hvp(plan->dseg, &plan->hseg, L, cp, st);
-    return finish(plan->sys->ctx);
+    return finish_plan(plan);
 }
 
 // The phases of V_eff and its gradient over every path of `base`.  ev, when given,
@@ -894,7 +909,7 @@ int veff_energy(mop_plan plan, const double* R, int32_t N, double* veff, double*
     const Launch L = one_path(N, N > 1 ? N - 1 : 1);
     path_sequence(plan->dseg, &plan->hseg, L, cp, false, 0, plan->waves, plan->newton3,
                   plan->sys->ctx->stream, nullptr, plan);
-    return finish(plan->sys->ctx);
+    return finish_plan(plan);
 }
 
 int veff_grad(mop_plan plan, const double* R, int32_t N, double* G, double* veff, int32_t mode,
@@ -911,7 +926,7 @@ int veff_grad(mop_plan plan, const double* R, int32_t N, double* G, double* veff
     const Launch L = one_path(N, N > 1 ? N - 1 : 1);
     path_sequence(plan->dseg, &plan->hseg, L, cp, true, mode, plan->waves, plan->newton3,
                   plan->sys->ctx->stream, nullptr, plan);
-    return finish(plan->sys->ctx);
+    return finish_plan(plan);
 }
 
 int veff_grad_timed(mop_plan plan, const double* R, int32_t N, double* G, double* veff,
@@ -932,7 +947,7 @@ int veff_grad_timed(mop_plan plan, const double* R, int32_t N, double* G, double
     const Launch L = one_path(N, N > 1 ? N - 1 : 1);
     path_sequence(plan->dseg, &plan->hseg, L, cp, true, mode, plan->waves, plan->newton3, st, ev,
                   plan);
-    int rc = finish(plan->sys->ctx);
+    int rc = finish_plan(plan);
     if (hipEventSynchronize(ev[MOP_NPHASES]) != hipSuccess) rc = MOP_EHIP;
     for (int k = 0; k < MOP_NPHASES; ++k) {
         float ms = 0.0f;
@@ -1076,7 +1091,7 @@ int pmd_step(mop_plan plan, mop_bias bias, double* R, double* V, double* G, int3
                      step % (uint64_t)bias->stride == 0 ? 1 : 0, cp.status, st);
         run_pmd_post(plan->dseg, &plan->hseg, L, V, G, pc, cp.ws, ek, 4, bias ? 1 : 0, st);
     }
-    return finish(plan->sys->ctx);
+    return finish_plan(plan);
 }
 
 int mop_batch_create(int32_t P, const mop_plan* plans, const int32_t* N, mop_batch* out) {
