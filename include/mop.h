@@ -322,10 +322,10 @@ int mop_status_clear(mop_plan plan, void* ws);
 #define MOP_NPHASES 8
 #define MOP_PHASE_BIN 0       /* fixed point, histogram, scans, scatter, padding */
 #define MOP_PHASE_FORCE 1     /* pair-force kernel, beads 1..N-1 (energy of bead 1) */
-#define MOP_PHASE_PME_FORCE 2 /* PME reciprocal forces (0 for reaction field) */
+#define MOP_PHASE_PME_FORCE 2 /* PME mesh forces beyond the pair kernel they run beside */
 #define MOP_PHASE_RESID 3     /* residuals, spring energy, FP32 copy of d */
 #define MOP_PHASE_HVP 4       /* pair Hessian-vector kernel (mode 0) */
-#define MOP_PHASE_PME_HVP 5   /* PME reciprocal Hessian-vector products (mode 0) */
+#define MOP_PHASE_PME_HVP 5   /* PME mesh Hessian-vector products beyond the pair kernel */
 #define MOP_PHASE_FD 6        /* (re-)binning + two force passes (modes 1, 2) */
 #define MOP_PHASE_ASSEMBLE 7  /* gradient assembly and V_eff reduction */
 int veff_grad_timed(mop_plan plan, const double* R, int32_t N, double* G, double* veff,

@@ -21,6 +21,16 @@ __device__ __forceinline__ bool finite3(double a, double b, double c) {
     return isfinite(a) && isfinite(b) && isfinite(c);
 }
 
+// PME systems: add the reciprocal-space force (or H v) of atom i of bead b, kept in FP64.
+__device__ __forceinline__ void add_mesh(const SegDev& sg, char* ws, size_t off, int b, int i,
+                                         double v[3]) {
+    if (sg.s.elec != 1) return;
+    const double* m = wsp<const double>(ws, off) + ((size_t)b * sg.s.Q + i) * 3;
+    v[0] += m[0];
+    v[1] += m[1];
+    v[2] += m[2];
+}
+
 __global__ void __launch_bounds__(EWB) k_resid(const SegDev* __restrict__ segs, Launch L,
                                                CallPtrs cp) {
     __shared__ double sh[EWB / 64];
@@ -39,6 +49,7 @@ __global__ void __launch_bounds__(EWB) k_resid(const SegDev* __restrict__ segs, 
         const double* Rn = cp.R + sg.roff + (size_t)n * Q * 3;
         const float4 fp = wsp<const float4>(ws, sg.o_f32)[(size_t)n * Q + i];
         double f[3] = {fp.x, fp.y, fp.z};
+        add_mesh(sg, ws, sg.o_frec, n, i, f);
         bond_force(s, Rn, nullptr, 0.0, i, f, n == 0 ? &eb : nullptr);
         if (n < N - 1) {
             const double* Rn1 = Rn + (size_t)Q * 3;
@@ -93,6 +104,7 @@ __global__ void __launch_bounds__(EWB) k_assemble(const SegDev* __restrict__ seg
     if (n == 0) {
         const float4 fp = wsp<const float4>(ws, sg.o_f32)[i];
         double f[3] = {fp.x, fp.y, fp.z};
+        add_mesh(sg, ws, sg.o_frec, 0, i, f);
         bond_force(s, cp.R + sg.roff, nullptr, 0.0, i, f, nullptr);
         for (int a = 0; a < 3; ++a) g[a] -= f[a];
     }
@@ -108,6 +120,7 @@ __global__ void __launch_bounds__(EWB) k_assemble(const SegDev* __restrict__ seg
         if (!fd) {
             const float4 hp = wsp<const float4>(ws, sg.o_hv32)[(size_t)n * Q + i];
             double hv[3] = {hp.x, hp.y, hp.z};
+            add_mesh(sg, ws, sg.o_hrec, n, i, hv);
             bond_hvp(s, Rn, Dn, i, hv);
             for (int a = 0; a < 3; ++a) g[a] += 0.5 * hv[a];
         } else {
@@ -217,6 +230,7 @@ __global__ void __launch_bounds__(EWB) k_finalize_forces(const SegDev* __restric
     if (i < Q) {
         const float4 fp = wsp<const float4>(cp.ws, sg.o_f32)[(size_t)b * Q + i];
         double f[3] = {fp.x, fp.y, fp.z};
+        add_mesh(sg, cp.ws, sg.o_frec, b, i, f);
         bond_force(sg.s, cp.R + sg.roff + (size_t)b * Q * 3, nullptr, 0.0, i, f, &eb);
         float* o = cp.Fout + sg.roff + ((size_t)b * Q + i) * 3;
         o[0] = (float)f[0];
@@ -274,6 +288,7 @@ __global__ void __launch_bounds__(EWB) k_finalize_hvp(const SegDev* __restrict__
     if (i >= Q) return;
     const float4 hp = wsp<const float4>(cp.ws, sg.o_hv32)[(size_t)b * Q + i];
     double hv[3] = {hp.x, hp.y, hp.z};
+    add_mesh(sg, cp.ws, sg.o_hrec, b, i, hv);
     bond_hvp(sg.s, cp.R + sg.roff + (size_t)b * Q * 3, cp.V + sg.roff + (size_t)b * Q * 3, i, hv);
     float* o = cp.Fout + sg.roff + ((size_t)b * Q + i) * 3;
     o[0] = (float)hv[0];

@@ -427,9 +427,9 @@ __global__ void __launch_bounds__(PME_BLOCK) k_pme_solve(const SegDev* __restric
     }
 }
 
-// KIND 0: forces from phi (pphi, or pgr for displaced configurations) added to the
-// float4 output (outsel 0: f32, 1: hv32, 2: f32m).  KIND 1: H v from pphi and the
-// dipole potential in pgr, added to hv32.
+// KIND 0: forces from phi (pphi, or pgr for displaced configurations); KIND 1: H v
+// from pphi and the dipole potential in pgr.  outsel 0, 1, 2: added to the float4 pair
+// output f32, hv32, f32m; outsel 3, 4: written to the FP64 buffer frec, hrec.
 template <int P, int KIND>
 __global__ void __launch_bounds__(EWB) k_pme_gather(const SegDev* __restrict__ segs, int nb,
                                                     char* ws, const double* __restrict__ R,
@@ -514,6 +514,13 @@ __global__ void __launch_bounds__(EWB) k_pme_gather(const SegDev* __restrict__ s
         o[0] = qi * s.kl[0] * ax;
         o[1] = qi * s.kl[1] * ay;
         o[2] = qi * s.kl[2] * az;
+    }
+    if (outsel >= 3) {
+        double* d = wsp<double>(ws, outsel == 3 ? sg.o_frec : sg.o_hrec) + ((size_t)b * s.Q + i) * 3;
+        d[0] = o[0];
+        d[1] = o[1];
+        d[2] = o[2];
+        return;
     }
     size_t off = sg.o_f32;
     if (outsel == 1) off = sg.o_hv32;

@@ -66,7 +66,8 @@ void run_pme_spread(const SegDev* dsegs, const SegDev& h, int nb, int nbatch, ch
                     hipStream_t st);
 void run_pme_solve(const SegDev* dsegs, const SegDev& h, int nb, char* ws, int want_e,
                    hipStream_t st);
-// outsel: 0 f32, 1 hv32, 2 f32m; use_pgr: kind-0 potential read from pgr instead of pphi.
+// outsel: added to 0 f32, 1 hv32, 2 f32m (float4); written to 3 frec, 4 hrec (FP64);
+// use_pgr: kind-0 potential read from pgr instead of pphi.
 void run_pme_gather(const SegDev* dsegs, const SegDev& h, int nb, char* ws, const double* R,
                     const double* V, int kind, int fdsign, double fdh, int outsel, int use_pgr,
                     hipStream_t st);

@@ -63,6 +63,10 @@ struct mop_plan_s {
     size_t ws_bytes;
     PmeFft fft;           // PME systems
     mutable bool fft_failed = false;  // a transform could not be enqueued (reported by the call)
+    // PME systems: the mesh work runs on a second stream, forked from and joined to the
+    // context stream with events, concurrently with the pair kernels
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
 };
 
 struct mop_bias_s {
@@ -287,7 +291,7 @@ static size_t layout(SegDev& sg, int maxb, int maxN, size_t base) {
         take(sg.o_nlc, B * s.cpb * 4);
     }
     sg.o_ptc = sg.o_pts = sg.o_ptid = sg.o_ptrk = sg.o_ptb = sg.o_ptw = 0;
-    sg.o_pgr = sg.o_pgc = sg.o_pphi = sg.o_pep = sg.o_pfw = 0;
+    sg.o_pgr = sg.o_pgc = sg.o_pphi = sg.o_pep = sg.o_pfw = sg.o_frec = sg.o_hrec = 0;
     if (s.elec == 1) {
         const size_t Kt = (size_t)s.Kg[0] * s.Kg[1] * s.Kg[2];
         const size_t Kc = (size_t)s.Kg[0] * s.Kg[1] * s.Kzh;
@@ -301,6 +305,8 @@ static size_t layout(SegDev& sg, int maxb, int maxN, size_t base) {
         take(sg.o_pgc, B * Kc * 16);
         take(sg.o_pphi, B * Kt * 8);
         take(sg.o_pep, B * (size_t)s.nsb * 8);
+        take(sg.o_frec, B * Q * 24);
+        take(sg.o_hrec, B * Q * 24);
     }
     sg.maxb = maxb;
     sg.maxN = maxN;
@@ -687,8 +693,16 @@ int mop_plan_create(mop_system sys, int32_t max_beads, const mop_plan_opts* opts
     pl->ws_bytes = layout(pl->hseg, max_beads, max_beads, 256);
     pl->dseg = nullptr;
     if (pl->hseg.s.elec == 1) {
-        const int e = make_fft(pl->fft, pl->hseg.s.Kg, pl->hseg.maxb);
+        int e = make_fft(pl->fft, pl->hseg.s.Kg, pl->hseg.maxb);
+        if (!e && (hipStreamCreateWithFlags(&pl->side, hipStreamNonBlocking) != hipSuccess ||
+                   hipEventCreateWithFlags(&pl->fork, hipEventDisableTiming) != hipSuccess ||
+                   hipEventCreateWithFlags(&pl->join, hipEventDisableTiming) != hipSuccess))
+            e = MOP_EHIP;
         if (e) {
+            destroy_fft(pl->fft);
+            if (pl->side) (void)hipStreamDestroy(pl->side);
+            if (pl->fork) (void)hipEventDestroy(pl->fork);
+            if (pl->join) (void)hipEventDestroy(pl->join);
             delete pl;
             return e;
         }
@@ -696,14 +710,12 @@ int mop_plan_create(mop_system sys, int32_t max_beads, const mop_plan_opts* opts
         pl->ws_bytes = pl->hseg.o_pfw + std::max<size_t>(pl->fft.work, 256);
     }
     if (hipMalloc(&pl->dseg, sizeof(SegDev)) != hipSuccess) {
-        destroy_fft(pl->fft);
-        delete pl;
+        pl->dseg = nullptr;
+        mop_plan_destroy(pl);
         return MOP_ENOMEM;
     }
     if (hipMemcpy(pl->dseg, &pl->hseg, sizeof(SegDev), hipMemcpyHostToDevice) != hipSuccess) {
-        (void)hipFree(pl->dseg);
-        destroy_fft(pl->fft);
-        delete pl;
+        mop_plan_destroy(pl);
         return MOP_EHIP;
     }
     *out = pl;
@@ -714,6 +726,9 @@ void mop_plan_destroy(mop_plan plan) {
     if (!plan) return;
     if (plan->dseg) (void)hipFree(plan->dseg);
     destroy_fft(plan->fft);
+    if (plan->side) (void)hipStreamDestroy(plan->side);
+    if (plan->fork) (void)hipEventDestroy(plan->fork);
+    if (plan->join) (void)hipEventDestroy(plan->join);
     delete plan;
 }
 
@@ -772,10 +787,11 @@ static int finish_plan(mop_plan plan) {
     return rc;
 }
 
-// PME reciprocal forces of nb pair beads at R (displaced by fdsign eps d), added to the
-// float4 output outsel (when gather); the potential goes to pphi for the undisplaced
-// configuration (kept for the Hessian pass), else to pgr.  Energy partials are formed
-// for the undisplaced configuration.
+// PME reciprocal forces of nb pair beads at R (displaced by fdsign eps d) into output
+// outsel of the gather (when gather): 3 = the FP64 buffer frec, 1 / 2 = added to the
+// float4 buffers of the displaced force passes.  The potential goes to pphi for the
+// undisplaced configuration (kept for the Hessian pass), else to pgr.  Energy partials
+// are formed for the undisplaced configuration.
 static void pme_forces(const mop_plan_s* pl, int nb, const CallPtrs& cp, int fdsign, int outsel,
                        bool gather, hipStream_t st) {
     const SegDev& h = pl->hseg;
@@ -791,7 +807,7 @@ static void pme_forces(const mop_plan_s* pl, int nb, const CallPtrs& cp, int fds
 }
 
 // PME reciprocal H v of nb pair beads (V: [nb][Q][3]; needs pphi and the tile order of
-// the same beads from pme_forces, and the per-bead max |v|^2), added to hv32.
+// the same beads from pme_forces, and the per-bead max |v|^2), written to hrec.
 static void pme_hvp(const mop_plan_s* pl, int nb, const CallPtrs& cp, const double* V,
                     hipStream_t st) {
     const SegDev& h = pl->hseg;
@@ -800,7 +816,19 @@ static void pme_hvp(const mop_plan_s* pl, int nb, const CallPtrs& cp, const doub
     run_fft(pl, true, ws + h.o_pgr, ws + h.o_pgc, ws + h.o_pfw, st);
     run_pme_solve(pl->dseg, h, nb, ws, 0, st);
     run_fft(pl, false, ws + h.o_pgc, ws + h.o_pgr, ws + h.o_pfw, st);
-    run_pme_gather(pl->dseg, h, nb, ws, cp.R, V, 1, 0, 0.0, 1, 0, st);
+    run_pme_gather(pl->dseg, h, nb, ws, cp.R, V, 1, 0, 0.0, 4, 0, st);
+}
+
+// Fork: work enqueued on the plan's side stream after this waits for everything enqueued
+// on st so far.  Join: work enqueued on st after this waits for the side stream.
+static void fork_side(const mop_plan_s* pl, hipStream_t st) {
+    (void)hipEventRecord(pl->fork, st);
+    (void)hipStreamWaitEvent(pl->side, pl->fork, 0);
+}
+
+static void join_side(const mop_plan_s* pl, hipStream_t st) {
+    (void)hipEventRecord(pl->join, pl->side);
+    (void)hipStreamWaitEvent(st, pl->join, 0);
 }
 
 int bead_forces(mop_plan plan, const double* R, int32_t B, float* F, double* U, void* ws) {
@@ -813,9 +841,14 @@ int bead_forces(mop_plan plan, const double* R, int32_t B, float* F, double* U, 
     cp.Fout = F;
     cp.Uout = U;
     const Launch L = one_path(B, B);
+    const bool pme = plan->hseg.s.elec == 1;
+    if (pme) {
+        fork_side(plan, st);
+        pme_forces(plan, B, cp, 0, 3, true, plan->side);
+    }
     run_binning(plan->dseg, &plan->hseg, L, cp.ws, R, 0, 0.0, st);
     run_pair(plan->dseg, &plan->hseg, L, cp.ws, 0, 0, U ? -2 : -1, plan->waves, plan->newton3, st);
-    if (plan->hseg.s.elec == 1) pme_forces(plan, B, cp, 0, 0, true, st);
+    if (pme) join_side(plan, st);
     run_finalize_forces(plan->dseg, &plan->hseg, L, cp, st);
     return finish_plan(plan);
 }
@@ -830,14 +863,18 @@ int bead_hvp(mop_plan plan, const double* R, const double* V, int32_t B, float* 
     cp.V = V;
     cp.Fout = HV;
     const Launch L = one_path(B, B);
+    const bool pme = plan->hseg.s.elec == 1;
     run_binning(plan->dseg, &plan->hseg, L, cp.ws, R, 0, 0.0, st);
+    if (pme) {
+        // after the binning, which clears the per-bead max |v|^2
+        fork_side(plan, st);
+        pme_forces(plan, B, cp, 0, 3, false, plan->side);
+        run_pme_vmax(plan->dseg, plan->hseg, B, cp.ws, V, plan->side);
+        pme_hvp(plan, B, cp, V, plan->side);
+    }
     run_prep_v(plan->dseg, &plan->hseg, L, cp, st);
     run_pair(plan->dseg, &plan->hseg, L, cp.ws, 1, 0, -1, plan->waves, plan->newton3, st);
-    if (plan->hseg.s.elec == 1) {
-        pme_forces(plan, B, cp, 0, 0, false, st);
-        run_pme_vmax(plan->dseg, plan->hseg, B, cp.ws, V, st);
-        pme_hvp(plan, B, cp, V, st);
-    }
+    if (pme) join_side(plan, st);
     run_finalize_hvp(plan->dseg, &plan->hseg, L, cp, st);
     return finish_plan(plan);
 }
@@ -853,6 +890,11 @@ static void path_sequence(const SegDev* dsegs, const SegDev* hsegs, const Launch
         if (ev) (void)hipEventRecord(ev[k], st);
     };
     mark(0);
+    // PME: the mesh forces run beside the binning and the pair forces
+    if (pme) {
+        fork_side(pl, st);
+        pme_forces(pl, base.nb[0], cp, 0, 3, true, pl->side);
+    }
     // forces of beads 1..N-1 (bead 1 alone for N = 1), energy of bead 1
     run_binning(dsegs, hsegs, base, cp.ws, cp.R, 0, 0.0, st);
     mark(1);
@@ -860,7 +902,7 @@ static void path_sequence(const SegDev* dsegs, const SegDev* hsegs, const Launch
     const int lists = (grad && mode == 0) ? 1 : 0;
     run_pair(dsegs, hsegs, base, cp.ws, 0, 0, 0, waves, n3, st, lists);
     mark(2);
-    if (pme) pme_forces(pl, base.nb[0], cp, 0, 0, true, st);
+    if (pme) join_side(pl, st);
     mark(3);
     run_resid(dsegs, hsegs, base, cp, st);
     mark(4);
@@ -871,10 +913,15 @@ static void path_sequence(const SegDev* dsegs, const SegDev* hsegs, const Launch
             Lh.nb[p] = base.N[p] - 1;
             any = any || Lh.nb[p] > 0;
         }
+        // PME: the mesh Hessian-vector products run beside the pair Hessian kernel
+        const bool mesh = any && mode == 0 && pme;
+        if (mesh) {
+            fork_side(pl, st);
+            pme_hvp(pl, Lh.nb[0], cp, wsp_host<double>(cp.ws, hsegs[0].o_d64), pl->side);
+        }
         if (any && mode == 0) run_pair(dsegs, hsegs, Lh, cp.ws, 1, 0, -1, waves, n3, st, 2 * lists);
         mark(5);
-        if (any && mode == 0 && pme)
-            pme_hvp(pl, Lh.nb[0], cp, wsp_host<double>(cp.ws, hsegs[0].o_d64), st);
+        if (mesh) join_side(pl, st);
         mark(6);
         if (any && mode != 0) {
             // mode 1 re-bins each displaced configuration; mode 2 keeps R's binning

@@ -25,6 +25,8 @@
 //     pgc   double2 [Kc]   half spectrum (Kc = Kx Ky (Kz/2 + 1))
 //     pphi  double [K]     grid potential of the force pass, kept for the Hessian pass
 //     pep   double [nsb]   energy partials of the solve kernel
+//     frec, hrec double [Q][3]  reciprocal forces / Hessian-vector products (original
+//                          order), added by the FP64 path kernels
 //   plus one FFT work buffer.
 #pragma once
 
@@ -122,7 +124,7 @@ struct SegDev {
     size_t o_upos, o_umeta, o_orig, o_slotof, o_atomu, o_rank, o_bincnt, o_binoff,
         o_colcnt, o_colstart, o_vs, o_fs, o_f32, o_f32m, o_hv32, o_epart, o_d64, o_rpart,
         o_dmax, o_eres, o_nl, o_nlc, o_tmpo, o_ptc, o_pts, o_ptid, o_ptrk, o_ptb, o_ptw, o_pgr, o_pgc,
-        o_pphi, o_pep, o_pfw;
+        o_pphi, o_pep, o_pfw, o_frec, o_hrec;
 };
 
 // Per-launch description, passed by value.
