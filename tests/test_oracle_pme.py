@@ -229,3 +229,20 @@ def test_cell_list_oracle_matches_brute_force_with_pme(name):
     assert c.energy(X) == pytest.approx(m.energy(X), rel=1e-12)
     assert np.max(np.abs(c.forces(X) - m.forces(X))) < 1e-12 * np.max(np.abs(m.forces(X)))
     assert np.max(np.abs(c.hvp(X, V) - m.hvp(X, V))) < 1e-12 * np.max(np.abs(m.hvp(X, V)))
+
+
+def test_pme_path_gradient_matches_finite_differences_of_veff():
+    """The exact path gradient of eqs. (5)-(7) with the PME Hessian-vector product is the
+    directional derivative of V_eff (eq. 3) with PME forces inside the residuals."""
+    from oracle import path as OPth
+    s = W.with_pme(W.tiny(Q=20, seed=11))
+    m = Model(s)
+    R, _, _ = W.random_walk_path(s, 4, 5, sigma=0.003)
+    G, _ = OPth.veff_grad(m, R)
+    rng = np.random.default_rng(7)
+    for _ in range(3):
+        u = rng.standard_normal(R.shape)
+        u /= np.linalg.norm(u)
+        h = 2e-6
+        fd = (OPth.veff(m, R + h * u)[0] - OPth.veff(m, R - h * u)[0]) / (2 * h)
+        assert abs(fd - np.sum(G * u)) < 2e-6 * np.linalg.norm(G)
