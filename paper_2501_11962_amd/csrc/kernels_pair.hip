@@ -54,8 +54,9 @@
 
 namespace mop {
 
-// Ring fields (one LDS array [field][entry] per wave; ints stored as float bits).
-constexpr int F_X = 0, F_Y = 1, F_Z = 2, F_Q = 3, F_K = 4, F_T = 5, F_S = 6, F_J = 7;
+// Ring fields (one LDS array [field][entry] per wave; ints stored as float bits).  F_K
+// holds the packed word 16 * exclusion key + LJ type of the system's key table.
+constexpr int F_X = 0, F_Y = 1, F_Z = 2, F_Q = 3, F_K = 4, F_S = 5, F_J = 6;
 
 // Table entries per type pair in LDS, 16 bytes apart: the force kernels keep
 // {a12, a6, csf, e0lj} for the nt^2 pairs followed by {b12, b6, c12, c6} (energies);
@@ -80,14 +81,15 @@ __device__ __forceinline__ float erfc_ex2(float x, float ex2) {
 
 template <int MODE, int N3>
 struct Fields {
-    static constexpr int V = N3 ? 10 : 7;                    // v_j (HVP only)
-    static constexpr int NF = MODE == 1 ? V + 3 : (N3 ? 10 : 7);
+    static constexpr int V = N3 ? F_J + 3 : F_K + 1;  // v_j (HVP only)
+    static constexpr int NF = MODE == 1 ? V + 3 : V;
 };
 
 struct IAtom {
     float x, y, z, q, vx, vy, vz;
     uint32_t ux, uy, uz;
-    int key2, tiN;
+    uint32_t kp;  // 16 * (key + 2) + 15, from the packed word 16 * key + type
+    int tiN;
     bool v;
 };
 
@@ -110,7 +112,7 @@ template <int MODE, bool EX, bool WANTE, bool T_OUT, int EL, bool Q3 = false>
 __device__ __forceinline__ void pair_term(const IAtom& I, const PairK& P, const float4* tabrow,
                                           int ntab,
                                           float jx, float jy, float jz,
-                                          float qj, int kj, int tj, float vjx, float vjy,
+                                          float qj, uint32_t kj, float vjx, float vjy,
                                           float vjz, bool valid, float& ax, float& ay,
                                           float& az, float& tx, float& ty, float& tz,
                                           float& en) {
@@ -125,11 +127,15 @@ __device__ __forceinline__ void pair_term(const IAtom& I, const PairK& P, const 
         dz = jz - I.z;
     }
     const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-    // same molecule within two chain positions (the atom itself: I.key2 - kj == 2)
-    const bool exc = (unsigned)(I.key2 - kj) <= 4u;
+    // kj = 16 key_j + type_j, so I.kp - kj = 16 (key_i - key_j + 2) + 15 - type_j (keys
+    // below 2^27, no wrap-around): it lies in [0, 79] exactly when |key_i - key_j| <= 2
+    // (same molecule within two chain positions), and in [32, 47] for the atom itself
+    const uint32_t kd = I.kp - kj;
+    const int tj = (int)(kj & 15u);
+    const bool exc = kd <= 79u;
     const bool near = valid & I.v & (r2 < P.rc2);
     const bool in = near & !exc;
-    const bool cor = EL == 1 && near && exc && (I.key2 - kj != 2);  // Ewald correction
+    const bool cor = EL == 1 && near && exc && (kd - 32u > 15u);  // Ewald correction
     // masked lanes (self pair at r = 0, stale ring entries) may form inf/NaN here; every
     // result they feed is replaced by 0 through a select below, never multiplied
     const float r2s = r2;
@@ -295,7 +301,7 @@ __global__ void __launch_bounds__(64 * PW, EL == 1 ? 4 : 1) k_pair(const SegDev*
     IAtom I;
     I.v = mi.x != DUMMY_KEY;
     I.q = __uint_as_float(ui.w);
-    I.key2 = mi.x + 2;
+    I.kp = (uint32_t)(mi.x - mi.y) + 47u;
     I.tiN = mi.y * nt;
     const float4* tabrow = s_tab + I.tiN;
     const int ntab = nt * nt;
@@ -438,17 +444,17 @@ __global__ void __launch_bounds__(64 * PW, EL == 1 ? 4 : 1) k_pair(const SegDev*
         const float qj = __uint_as_float(uj.w);
         if (exact) {
             if (wantE)
-                pair_term<MODE, true, true, false, EL>(I, P, tabrow, ntab, jx, jy, jz, qj, mj.x, mj.y, vjx,
+                pair_term<MODE, true, true, false, EL>(I, P, tabrow, ntab, jx, jy, jz, qj, (uint32_t)mj.x, vjx,
                                             vjy, vjz, vj, ax, ay, az, tx, ty, tz, en);
             else
-                pair_term<MODE, true, false, false, EL>(I, P, tabrow, ntab, jx, jy, jz, qj, mj.x, mj.y, vjx,
+                pair_term<MODE, true, false, false, EL>(I, P, tabrow, ntab, jx, jy, jz, qj, (uint32_t)mj.x, vjx,
                                              vjy, vjz, vj, ax, ay, az, tx, ty, tz, en);
         } else {
             if (wantE)
-                pair_term<MODE, false, true, false, EL>(I, P, tabrow, ntab, jx, jy, jz, qj, mj.x, mj.y, vjx,
+                pair_term<MODE, false, true, false, EL>(I, P, tabrow, ntab, jx, jy, jz, qj, (uint32_t)mj.x, vjx,
                                              vjy, vjz, vj, ax, ay, az, tx, ty, tz, en);
             else
-                pair_term<MODE, false, false, false, EL>(I, P, tabrow, ntab, jx, jy, jz, qj, mj.x, mj.y, vjx,
+                pair_term<MODE, false, false, false, EL>(I, P, tabrow, ntab, jx, jy, jz, qj, (uint32_t)mj.x, vjx,
                                               vjy, vjz, vj, ax, ay, az, tx, ty, tz, en);
         }
         eacc += 0.5f * en;
@@ -466,8 +472,7 @@ __global__ void __launch_bounds__(64 * PW, EL == 1 ? 4 : 1) k_pair(const SegDev*
             const int o = s * 8;
             const float jx = rb[F_X * RING + o], jy = rb[F_Y * RING + o], jz = rb[F_Z * RING + o];
             const float qj = rb[F_Q * RING + o];
-            const int kj = __float_as_int(rb[F_K * RING + o]);
-            const int tj = __float_as_int(rb[F_T * RING + o]);
+            const uint32_t kj = __float_as_uint(rb[F_K * RING + o]);
             float vjx = 0.f, vjy = 0.f, vjz = 0.f;
             if (MODE == 1) {
                 vjx = rb[FV * RING + o];
@@ -479,13 +484,13 @@ __global__ void __launch_bounds__(64 * PW, EL == 1 ? 4 : 1) k_pair(const SegDev*
             // in this wave's lifetime): masked products are still formed (0 * dx, 0 * dv),
             // so give them finite operands and a valid table index.
             float jxv = jx, jyv = jy, jzv = jz, qjv = qj;
-            int tjv = tj;
+            uint32_t kjv = kj;
             if (!FULL) {
                 jxv = valid ? jx : 0.0f;
                 jyv = valid ? jy : 0.0f;
                 jzv = valid ? jz : 0.0f;
                 qjv = valid ? qj : 0.0f;
-                tjv = valid ? tj : 0;
+                kjv = valid ? kj : 0u;
                 if (MODE == 1) {
                     vjx = valid ? vjx : 0.0f;
                     vjy = valid ? vjy : 0.0f;
@@ -493,7 +498,7 @@ __global__ void __launch_bounds__(64 * PW, EL == 1 ? 4 : 1) k_pair(const SegDev*
                 }
             }
             float tx, ty, tz, en = 0.f;
-            pair_term<MODE, EX, WE, N3 == 1, EL, THREE_Q<MODE, N3, EL>>(I, P, tabrow, ntab, jxv, jyv, jzv, qjv, kj, tjv, vjx, vjy,
+            pair_term<MODE, EX, WE, N3 == 1, EL, THREE_Q<MODE, N3, EL>>(I, P, tabrow, ntab, jxv, jyv, jzv, qjv, kjv, vjx, vjy,
                                              vjz, valid, ax, ay, az, tx, ty, tz, en);
             if (WE) eacc += N3 ? en : 0.5f * en;
             if (N3) {
@@ -572,7 +577,7 @@ __global__ void __launch_bounds__(64 * PW, EL == 1 ? 4 : 1) k_pair(const SegDev*
                 jz = __uint_as_float(uj.z);
             }
             const float jq = __uint_as_float(uj.w);
-            const int jk = mj.x, jt = mj.y;
+            const int jk = mj.x;
             const unsigned long long m = __ballot(pass);
             const int off = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
                                                       __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
@@ -585,7 +590,6 @@ __global__ void __launch_bounds__(64 * PW, EL == 1 ? 4 : 1) k_pair(const SegDev*
                 re[F_Z * RING] = jz;
                 re[F_Q * RING] = QSC * jq;
                 re[F_K * RING] = __int_as_float(jk);
-                re[F_T * RING] = __int_as_float(jt);
                 if (N3) {
                     re[F_S * RING] = __int_as_float(slot);
                     re[(F_J + 0) * RING] = 0.0f;
@@ -643,7 +647,6 @@ __global__ void __launch_bounds__(64 * PW, EL == 1 ? 4 : 1) k_pair(const SegDev*
                 re[F_Z * RING] = jz;
                 re[F_Q * RING] = QSC * __uint_as_float(uj.w);
                 re[F_K * RING] = __int_as_float(mj.x);
-                re[F_T * RING] = __int_as_float(mj.y);
                 re[FV * RING] = jv.x;
                 re[(FV + 1) * RING] = jv.y;
                 re[(FV + 2) * RING] = jv.z;

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <map>
 #include <vector>
 
 #include "../../include/mop.h"
@@ -185,8 +186,11 @@ static double ewald_beta(double rc, double rtol) {
     return 0.5 * (lo + hi);
 }
 
-// Exclusion key per atom: molecule id * 2^sh + position along the chain, with
-// 2^sh >= max position + 3 so that |key_i - key_j| <= 2 only within a molecule.
+// Exclusion key per atom: the molecule's offset plus the position along its chain.
+// Molecules get offsets in the order of their ids, each one its largest position + 3
+// after the previous one, so |key_i - key_j| <= 2 only within a molecule and every key is
+// below Q + 3 * (number of molecules) <= 4 Q.  Keys must stay below 2^27: the pair kernels
+// keep key * 16 + LJ type in one 32-bit word.
 // Without explicit molecules the bonds must form linear chains (degree <= 2, no cycles),
 // which are walked from one end.
 static int make_keys(const mop_system_desc* d, std::vector<int>& key) {
@@ -227,16 +231,21 @@ static int make_keys(const mop_system_desc* d, std::vector<int>& key) {
         for (int i = 0; i < Q; ++i)
             if (!seen[i]) return MOP_ETOPOLOGY;  // an atom on a ring
     }
-    int maxpos = 0, maxmol = 0;
+    std::map<int, long long> off;  // molecule id -> largest position, then offset
     for (int i = 0; i < Q; ++i) {
-        maxpos = std::max(maxpos, pos[i]);
-        maxmol = std::max(maxmol, mol[i]);
+        auto it = off.find(mol[i]);
+        if (it == off.end()) off.emplace(mol[i], pos[i]);
+        else it->second = std::max<long long>(it->second, pos[i]);
     }
-    int sh = 0;
-    while ((1 << sh) < maxpos + 3) ++sh;
-    if ((double)maxmol * (double)(1 << sh) + maxpos >= 2147483000.0) return MOP_ETOPOLOGY;
+    long long next = 0;
+    for (auto& m : off) {
+        const long long len = m.second + 1;
+        m.second = next;
+        next += len + 2;
+    }
+    if (next >= (1LL << 27)) return MOP_ETOPOLOGY;
     key.resize(Q);
-    for (int i = 0; i < Q; ++i) key[i] = mol[i] * (1 << sh) + pos[i];
+    for (int i = 0; i < Q; ++i) key[i] = (int)(off[mol[i]] + pos[i]);
     return MOP_OK;
 }
 
@@ -581,6 +590,7 @@ int mop_system_create(mop_ctx ctx, const mop_system_desc* d, mop_system* out) {
     s.nbond_entries = 2 * d->nbonds;
     int e = 0;
     if (!e) e = upload(sys, qs.data(), Q, &s.qs);
+    for (int i = 0; i < Q; ++i) key[i] = key[i] * 16 + typ[i];  // type < MAXTYPES = 16
     if (!e) e = upload(sys, key.data(), Q, &s.key);
     if (!e) e = upload(sys, typ.data(), Q, &s.type);
     if (!e) e = upload(sys, c.data(), Q, &s.c);

@@ -6,7 +6,7 @@
 //   range is padded to a multiple of 8 so that it splits into 8-atom clusters; padding
 //   slots carry DUMMY_KEY.  Sorted arrays (structure of arrays, one entry per slot):
 //     upos  uint4  {x, y, z fixed point (box = 2^32 units), charge bits (float)}
-//     umeta int2   {exclusion key, LJ type}
+//     umeta int2   {16 * exclusion key + LJ type, LJ type}
 //     orig  int    atom index of the slot (-1 for padding)
 //     vs    float4 the vector of a Hessian-vector product, slot order
 //     fs    float  x3 pair sums in slot order (structure of arrays), Newton-3 kernels
@@ -42,7 +42,7 @@ constexpr int MAXSEG = 32;        // paths per launch
 constexpr int CLUSTER = 8;        // atoms per cluster
 constexpr int RING = 128;         // j-atom ring per wave (power of two, >= 2*64)
 constexpr int CLIST = 256;        // candidate-cluster list per wave
-constexpr int MAXTYPES = 16;      // LJ types
+constexpr int MAXTYPES = 16;      // LJ types (the type fills the low 4 bits of a packed key)
 constexpr int EWB = 256;          // block size of the elementwise kernels
 constexpr int32_t DUMMY_KEY = INT32_MIN;
 
@@ -74,7 +74,7 @@ struct SysDev {
     float crf1;       // 1/rc^2 - 2 k_rf rc: -phi_RF'(rc) / (q_i q_j)
     float e0rf;       // -rc * crf1
     const float* qs;      // [Q] charge * sqrt(f / eps_r)
-    const int* key;       // [Q] exclusion key: same molecule and |key_i - key_j| <= 2
+    const int* key;       // [Q] 16 * exclusion key + LJ type; excluded pairs: |key_i - key_j| <= 2
     const int* type;      // [Q]
     const double* c;      // [Q] dt / (m nu)
     const double* K;      // [Q] m nu / (2 dt)

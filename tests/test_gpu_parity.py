@@ -258,7 +258,7 @@ def test_autograd_function(mop, ctx):
     v = mop.VeffFn.apply(Rt, plan)
     (2.5 * v).backward()
     G, v2 = mop.veff_grad(plan, cuda(R))
-    # two calls may sum FP32 pair terms in a different order (atomic bin ranks)
+    # the autograd backward and the direct call are separate launches of the same kernels
     scale = float(G.abs().max())
     assert torch.allclose(Rt.grad, 2.5 * G, rtol=1e-5, atol=1e-6 * scale)
     assert abs(float(v) - float(v2[0])) < 1e-7 * abs(float(v2[0]))
@@ -425,6 +425,44 @@ def test_cfg4_full_size_sampled(mop, ctx, cl_oracle):
     ef = rel(Fg.cpu().numpy()[0], F[0])
     say(f"[cfg4] bead_forces relL2 {ef:.2e}")
     assert ef < TOL_F
+
+
+def test_cfg5_full_batch_sampled(mop, ctx, cl_oracle):
+    """The uneven batch at its benchmark size (24 water paths, Q 1.4e3..1.7e4, N 33..122,
+    1.2e7 atom*beads) in one call.  G^n depends only on beads n-1, n and n+1, so the
+    gradient of bead 1, of one interior bead and of bead N of every path equals that of
+    the 2- or 3-bead sub-path around it, which the FP64 cell-list oracle evaluates; V_eff
+    is checked whole on the paths of least work."""
+    from oracle import path as OPth
+    specs = W.cfg5()
+    rng = np.random.default_rng(5)
+    plans, paths, Rs = [], [], []
+    for s_, N, seed in specs:
+        R, _, _ = W.random_walk_path(s_, N, seed)
+        Rs.append(R)
+        plans.append(mop.Plan(mop.System(ctx, s_), N))
+        paths.append(cuda(R))
+    bt = mop.Batch(plans, [n for _, n, _ in specs])
+    Gflat, v = bt.veff_grad(bt.pack(paths))
+    assert bt.status() == 0
+    Gs = [g.cpu().numpy() for g in bt.unpack(Gflat)]
+    v = v.cpu().numpy()
+    worst = 0.0
+    for k, ((s_, N, _), R) in enumerate(zip(specs, Rs)):
+        m = cl_oracle.CellModel(s_)
+        n = int(rng.integers(1, N - 1))                      # interior bead (0-based)
+        G1, _ = OPth.veff_grad(m, np.ascontiguousarray(R[0:2]))
+        Gn, _ = OPth.veff_grad(m, np.ascontiguousarray(R[n - 1:n + 2]))
+        GN, _ = OPth.veff_grad(m, np.ascontiguousarray(R[N - 2:N]))
+        e = max(rel(Gs[k][0], G1[0]), rel(Gs[k][n], Gn[1]), rel(Gs[k][N - 1], GN[1]))
+        worst = max(worst, e)
+        assert e < TOL_G, (k, n, e)
+    order = np.argsort([s_["Q"] * N for s_, N, _ in specs])[:6]
+    for k in order:
+        s_, N, _ = specs[k]
+        vo = OPth.veff(cl_oracle.CellModel(s_), Rs[k])[0]
+        assert abs(float(v[k]) - vo) < TOL_V * abs(vo), (k, float(v[k]), vo)
+    say(f"[cfg5] {len(specs)} paths: worst G relL2 (beads 1, interior, N) {worst:.2e}")
 
 
 @pytest.mark.parametrize("name", ["water1002_cw03", "cfg2"])
