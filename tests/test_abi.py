@@ -80,6 +80,13 @@ def test_system_check_rejections(mop):
     assert mop.system_check(dict(s, bonds=b)) == -1
     sig = np.full(17, 0.3)
     assert mop.system_check(dict(s, sigma=sig, epsilon=sig)) == -3
+    # exclusion keys are numbered compactly, so sparse molecule ids are fine; a chain
+    # position that would push the keys past 2^27 is refused
+    sparse = dict(s, mol=np.asarray(s["mol"], np.int64) * 40000000 + 7)
+    assert mop.system_check(sparse, use_molecules=True) == 0
+    far = np.asarray(s["molpos"]).copy()
+    far[0] = 1 << 27
+    assert mop.system_check(dict(s, molpos=far), use_molecules=True) == -6
 
 
 def test_ctx_create_reports_missing_device(mop):
