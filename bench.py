@@ -74,12 +74,10 @@ def unique_pairs(system, X):
     return within - len(ex)
 
 
-def traffic_from_profiles(workload):
-    """HBM bytes per launch of the Hessian pair kernel measured by rocprofv3 counters
-    (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter reads for a plain copy of
-    known size), from the committed summary, if it was taken on the current kernel
-    source; else None."""
-    p = os.path.join(ROOT, "profiles", f"traffic_pair_hvp_{workload}.md")
+def profile_summary(name):
+    """The machine-readable lines (`- key: value`) of a committed counter summary under
+    profiles/, if it was taken on the current pair-kernel source; else None."""
+    p = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(p):
         return None
     kv = {}
@@ -88,10 +86,31 @@ def traffic_from_profiles(workload):
             k, v = line.strip()[2:].split(":", 1)
             kv[k.strip()] = v.strip().strip("`")
     h = hashlib.sha256(open(PAIR_SRC, "rb").read()).hexdigest()
-    if kv.get("kernel_source_sha256") != h:
-        return None
+    return kv if kv.get("kernel_source_sha256") == h else None
+
+
+def traffic_from_profiles(workload):
+    """HBM bytes per launch of the Hessian pair kernel measured by rocprofv3 counters
+    (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter reads for a plain copy of
+    known size), from the committed summary, if it was taken on the current kernel
+    source; else None."""
+    kv = profile_summary(f"traffic_pair_hvp_{workload}.md")
     try:
-        return int(float(kv["bytes_per_launch"]))
+        return int(float(kv["bytes_per_launch"])) if kv else None
+    except (KeyError, ValueError):
+        return None
+
+
+def executed_from_profiles(workload):
+    """Executed FP32 FLOPs per launch of the Hessian and force pair kernels, counted by
+    rocprofv3 (SQ_INSTS_VALU_FLOPS_FP32 counts each wave instruction once, so it is
+    multiplied by the 64 lanes; masked lanes are included), and their VALU instructions
+    per compute-unit cycle, from the committed summary if it matches the kernel source."""
+    kv = profile_summary(f"valu_pair_{workload}.md")
+    try:
+        return None if kv is None else {k: float(kv[k]) for k in (
+            "hvp_executed_flops_per_launch", "force_executed_flops_per_launch",
+            "hvp_valu_per_cu_cycle", "force_valu_per_cu_cycle")}
     except (KeyError, ValueError):
         return None
 
@@ -522,6 +541,17 @@ def main():
                 force_kernel=dict(achieved=round(flops_force / t_force / 1e12, 3),
                                   launch_ms=round(phases["force"], 4)),
                 whole_step_tflops=round((flops_hvp + flops_force) / (ms * 1e-3) / 1e12, 3))
+    ex = executed_from_profiles(args.config)
+    if ex:
+        # executed work (both sides of each pair, combinations beyond the cutoff, search
+        # and bookkeeping instructions) per launch, over this run's launch times
+        roof["executed"] = dict(
+            tflops=round(ex["hvp_executed_flops_per_launch"] / t_hvp / 1e12, 3),
+            frac=round(ex["hvp_executed_flops_per_launch"] / t_hvp / 1e12 / PEAK_FP32_TFLOPS, 4),
+            valu_per_cu_cycle=ex["hvp_valu_per_cu_cycle"],
+            source=f"profiles/valu_pair_{args.config}.md")
+        roof["force_kernel"]["executed_tflops"] = round(
+            ex["force_executed_flops_per_launch"] / t_force / 1e12, 3)
 
     out = dict(metric=METRIC, value=Q * N / (ms * 1e-3), unit="atom·beads/s", n_gpus=1,
                steps=args.steps, warmup=args.warmup, ms_per_step=ms, higher_is_better=True,
