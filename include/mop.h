@@ -130,6 +130,10 @@ typedef struct {
  *               gather the partner's share with atomic adds; summation order then
  *               depends on scheduling.  Default: every pair from both sides without
  *               atomics, which is the faster variant on MI355X.
+ *               MOP_PLAN_ONE_STREAM (PME systems): run the mesh work on the caller's
+ *               stream in call order instead of on a second stream of the plan beside
+ *               the pair kernels.  Results are bit-identical either way; for callers
+ *               that need every kernel on one stream, and for timing each kernel alone.
  *   list_cap    neighbour-list entries per 8-atom cluster.  veff_grad (exact mode)
  *               records, in its force pass, which atoms passed each cluster's
  *               neighbour search, and its Hessian pass reads them back instead of
@@ -139,6 +143,7 @@ typedef struct {
  *               4 * list_cap bytes per cluster and pair bead.
  */
 #define MOP_PLAN_NEWTON3 1
+#define MOP_PLAN_ONE_STREAM 2
 typedef struct {
     double col_width;
     double zbin;

@@ -65,7 +65,8 @@ struct mop_plan_s {
     PmeFft fft;           // PME systems
     mutable bool fft_failed = false;  // a transform could not be enqueued (reported by the call)
     // PME systems: the mesh work runs on a second stream, forked from and joined to the
-    // context stream with events, concurrently with the pair kernels
+    // context stream with events, concurrently with the pair kernels (unless one_stream)
+    int one_stream = 0;
     hipStream_t side = nullptr;
     hipEvent_t fork = nullptr, join = nullptr;
 };
@@ -686,6 +687,7 @@ static void run_fft(const mop_plan_s* pl, bool forward, void* in, void* out, voi
 int mop_plan_create(mop_system sys, int32_t max_beads, const mop_plan_opts* opts, mop_plan* out) {
     if (!sys || !out || max_beads < 1) return MOP_EINVAL;
     *out = nullptr;
+    if (opts && (opts->flags & ~(MOP_PLAN_NEWTON3 | MOP_PLAN_ONE_STREAM))) return MOP_EINVAL;
     if (sys->dev.elec == 1 && opts && (opts->flags & MOP_PLAN_NEWTON3)) return MOP_EINVAL;
     int waves = opts && opts->waves ? opts->waves : 4;
     if (waves != 1 && waves != 2 && waves != 4 && waves != 8) return MOP_EINVAL;
@@ -697,6 +699,7 @@ int mop_plan_create(mop_system sys, int32_t max_beads, const mop_plan_opts* opts
     pl->max_beads = max_beads;
     pl->waves = waves;
     pl->newton3 = (opts && (opts->flags & MOP_PLAN_NEWTON3)) ? 1 : 0;
+    pl->one_stream = (opts && (opts->flags & MOP_PLAN_ONE_STREAM)) ? 1 : 0;
     base_seg(pl->hseg, plan_geometry(sys, opts));
     pl->hseg.roff = 0;
     pl->hseg.vidx = 0;
@@ -704,9 +707,10 @@ int mop_plan_create(mop_system sys, int32_t max_beads, const mop_plan_opts* opts
     pl->dseg = nullptr;
     if (pl->hseg.s.elec == 1) {
         int e = make_fft(pl->fft, pl->hseg.s.Kg, pl->hseg.maxb);
-        if (!e && (hipStreamCreateWithFlags(&pl->side, hipStreamNonBlocking) != hipSuccess ||
-                   hipEventCreateWithFlags(&pl->fork, hipEventDisableTiming) != hipSuccess ||
-                   hipEventCreateWithFlags(&pl->join, hipEventDisableTiming) != hipSuccess))
+        if (!e && !pl->one_stream &&
+            (hipStreamCreateWithFlags(&pl->side, hipStreamNonBlocking) != hipSuccess ||
+             hipEventCreateWithFlags(&pl->fork, hipEventDisableTiming) != hipSuccess ||
+             hipEventCreateWithFlags(&pl->join, hipEventDisableTiming) != hipSuccess))
             e = MOP_EHIP;
         if (e) {
             destroy_fft(pl->fft);
@@ -830,13 +834,20 @@ static void pme_hvp(const mop_plan_s* pl, int nb, const CallPtrs& cp, const doub
 }
 
 // Fork: work enqueued on the plan's side stream after this waits for everything enqueued
-// on st so far.  Join: work enqueued on st after this waits for the side stream.
+// on st so far.  Join: work enqueued on st after this waits for the side stream.  With
+// MOP_PLAN_ONE_STREAM the mesh work goes to st itself and both are no-ops.
+static hipStream_t mesh_stream(const mop_plan_s* pl, hipStream_t st) {
+    return pl->one_stream ? st : pl->side;
+}
+
 static void fork_side(const mop_plan_s* pl, hipStream_t st) {
+    if (pl->one_stream) return;
     (void)hipEventRecord(pl->fork, st);
     (void)hipStreamWaitEvent(pl->side, pl->fork, 0);
 }
 
 static void join_side(const mop_plan_s* pl, hipStream_t st) {
+    if (pl->one_stream) return;
     (void)hipEventRecord(pl->join, pl->side);
     (void)hipStreamWaitEvent(st, pl->join, 0);
 }
@@ -854,7 +865,7 @@ int bead_forces(mop_plan plan, const double* R, int32_t B, float* F, double* U, 
     const bool pme = plan->hseg.s.elec == 1;
     if (pme) {
         fork_side(plan, st);
-        pme_forces(plan, B, cp, 0, 3, true, plan->side);
+        pme_forces(plan, B, cp, 0, 3, true, mesh_stream(plan, st));
     }
     run_binning(plan->dseg, &plan->hseg, L, cp.ws, R, 0, 0.0, st);
     run_pair(plan->dseg, &plan->hseg, L, cp.ws, 0, 0, U ? -2 : -1, plan->waves, plan->newton3, st);
@@ -878,9 +889,9 @@ int bead_hvp(mop_plan plan, const double* R, const double* V, int32_t B, float* 
     if (pme) {
         // after the binning, which clears the per-bead max |v|^2
         fork_side(plan, st);
-        pme_forces(plan, B, cp, 0, 3, false, plan->side);
-        run_pme_vmax(plan->dseg, plan->hseg, B, cp.ws, V, plan->side);
-        pme_hvp(plan, B, cp, V, plan->side);
+        pme_forces(plan, B, cp, 0, 3, false, mesh_stream(plan, st));
+        run_pme_vmax(plan->dseg, plan->hseg, B, cp.ws, V, mesh_stream(plan, st));
+        pme_hvp(plan, B, cp, V, mesh_stream(plan, st));
     }
     run_prep_v(plan->dseg, &plan->hseg, L, cp, st);
     run_pair(plan->dseg, &plan->hseg, L, cp.ws, 1, 0, -1, plan->waves, plan->newton3, st);
@@ -896,12 +907,14 @@ static void path_sequence(const SegDev* dsegs, const SegDev* hsegs, const Launch
                           const CallPtrs& cp, bool grad, int mode, int waves, int n3,
                           hipStream_t st, hipEvent_t* ev = nullptr, const mop_plan_s* pl = nullptr) {
     const bool pme = pl && pl->hseg.s.elec == 1;
+    const bool side = pme && !pl->one_stream;
     auto mark = [&](int k) {
         if (ev) (void)hipEventRecord(ev[k], st);
     };
     mark(0);
-    // PME: the mesh forces run beside the binning and the pair forces
-    if (pme) {
+    // PME: the mesh forces run beside the binning and the pair forces (on one stream:
+    // after them, as a phase of their own)
+    if (side) {
         fork_side(pl, st);
         pme_forces(pl, base.nb[0], cp, 0, 3, true, pl->side);
     }
@@ -912,7 +925,8 @@ static void path_sequence(const SegDev* dsegs, const SegDev* hsegs, const Launch
     const int lists = (grad && mode == 0) ? 1 : 0;
     run_pair(dsegs, hsegs, base, cp.ws, 0, 0, 0, waves, n3, st, lists);
     mark(2);
-    if (pme) join_side(pl, st);
+    if (side) join_side(pl, st);
+    else if (pme) pme_forces(pl, base.nb[0], cp, 0, 3, true, st);
     mark(3);
     run_resid(dsegs, hsegs, base, cp, st);
     mark(4);
@@ -925,13 +939,15 @@ static void path_sequence(const SegDev* dsegs, const SegDev* hsegs, const Launch
         }
         // PME: the mesh Hessian-vector products run beside the pair Hessian kernel
         const bool mesh = any && mode == 0 && pme;
-        if (mesh) {
+        const double* d64 = mesh ? wsp_host<double>(cp.ws, hsegs[0].o_d64) : nullptr;
+        if (mesh && side) {
             fork_side(pl, st);
-            pme_hvp(pl, Lh.nb[0], cp, wsp_host<double>(cp.ws, hsegs[0].o_d64), pl->side);
+            pme_hvp(pl, Lh.nb[0], cp, d64, pl->side);
         }
         if (any && mode == 0) run_pair(dsegs, hsegs, Lh, cp.ws, 1, 0, -1, waves, n3, st, 2 * lists);
         mark(5);
-        if (mesh) join_side(pl, st);
+        if (mesh && side) join_side(pl, st);
+        else if (mesh) pme_hvp(pl, Lh.nb[0], cp, d64, st);
         mark(6);
         if (any && mode != 0) {
             // mode 1 re-bins each displaced configuration; mode 2 keeps R's binning

@@ -44,6 +44,20 @@ def test_library_exports_every_declared_symbol(mop):
     assert set(names) == set(mop.EXPORTS)
 
 
+def test_binding_constants_match_the_header(mop):
+    """Every MOP_* constant the Python binding defines has the header's value, and the
+    binding's phase names follow the header's phase indices."""
+    h = open(os.path.join(ROOT, "include", "mop.h")).read()
+    d = {m.group(1): int(m.group(2)) for m in re.finditer(r"#define (MOP_\w+)\s+\(?(-?\d+)\)?", h)}
+    names = [k for k in dir(mop) if k.startswith("MOP_")]
+    assert names
+    for k in names:
+        assert d[k] == getattr(mop, k), k
+    assert len(mop.PHASES) == d["MOP_NPHASES"]
+    for i, ph in enumerate(mop.PHASES):
+        assert d["MOP_PHASE_" + ph.upper()] == i
+
+
 def test_strerror(mop):
     L = mop.lib()
     for code in (0, -1, -2, -3, -4, -5, -6, -7):

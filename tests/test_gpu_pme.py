@@ -169,6 +169,33 @@ def test_pme_repeated_calls_bit_identical(mop, ctx):
         assert np.array_equal(H0, mop.bead_hvp(plan, Rt, Vt).cpu().numpy())
 
 
+def test_pme_one_stream_plan_is_bit_identical(mop, ctx):
+    """MOP_PLAN_ONE_STREAM puts the mesh work on the caller's stream (after the pair
+    kernels) instead of a second stream beside them: every result is bit-identical, in
+    both gradient modes and through bead_forces / bead_hvp; unknown plan flags are refused."""
+    import ctypes as C
+    s = W.with_pme(W.water_box(1002, seed=9, rc=1.0))
+    N = 4
+    R, _, _ = W.random_walk_path(s, N, 31)
+    sysm = mop.System(ctx, s)
+    plans = [mop.Plan(sysm, N), mop.Plan(sysm, N, one_stream=True)]
+    Rt = cuda(R)
+    Vt = cuda(np.random.default_rng(4).normal(0.0, 1e-3, R.shape))
+    out = []
+    for pl in plans:
+        G, v = (x.cpu().numpy() for x in mop.veff_grad(pl, Rt))
+        Gf, vf = (x.cpu().numpy() for x in mop.veff_grad(pl, Rt, 1, 1e-4))
+        F, U = (x.cpu().numpy() for x in mop.bead_forces(pl, Rt))
+        H = mop.bead_hvp(pl, Rt, Vt).cpu().numpy()
+        assert pl.status() == 0
+        out.append((G, v, Gf, vf, F, U, H))
+    for a, b in zip(*out):
+        assert np.array_equal(a, b)
+    o = mop._Opts(0.0, 0.0, 0, 4, 0)
+    h = C.c_void_p()
+    assert mop.lib().mop_plan_create(sysm.h, N, C.byref(o), C.byref(h)) == -1  # MOP_EINVAL
+
+
 def test_pme_graph_replay_matches_eager(mop, ctx):
     """veff_grad of a PME system (pair kernels, spreading, rocFFT, gathers) captured in
     one graph; every replay, with eager work between replays, equals the eager call."""
