@@ -420,7 +420,7 @@ def main():
                          "kernel that scales HBM byte counters read by a profiler)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (--gpus {args.gpus} requested): this build "
+        print(f"bench.py measures one GPU only (--gpus {args.gpus} requested): the library "
               f"has no multi-GPU path; run with --gpus 1.", flush=True)
         sys.exit(2)
 
