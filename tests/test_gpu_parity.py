@@ -296,6 +296,29 @@ def test_cfg3_parity(cfg, N, mop, ctx, cl_oracle):
     assert abs(float(v[0]) - vo) < TOL_V * abs(vo)
 
 
+@pytest.mark.parametrize("cfg", ["cfg2", "cfg3"])
+def test_full_size_config_sampled(cfg, mop, ctx, cl_oracle):
+    """The water box (3,000 atoms x 64 beads) and the mixed-chain box (23,000 x 128) at
+    their full sizes, in the launch configuration bench.py times.  G^n depends only on
+    beads n-1, n and n+1, so beads 1, N and three interior beads are checked through the
+    2- and 3-bead sub-paths around them; V_eff is checked whole."""
+    s, R = W.make_config(cfg)
+    N = R.shape[0]
+    plan = mop.Plan(mop.System(ctx, s), N)
+    G, v = mop.veff_grad(plan, cuda(R))
+    assert plan.status() == 0
+    G = G.cpu().numpy()
+    m = cl_oracle.CellModel(s)
+    errs = [rel(G[0], OP.veff_grad(m, np.ascontiguousarray(R[0:2]))[0][0]),
+            rel(G[N - 1], OP.veff_grad(m, np.ascontiguousarray(R[N - 2:N]))[0][1])]
+    for n in np.random.default_rng(6).choice(np.arange(1, N - 1), 3, replace=False):
+        errs.append(rel(G[n], OP.veff_grad(m, np.ascontiguousarray(R[n - 1:n + 2]))[0][1]))
+    vo = OP.veff(m, R)[0]
+    say(f"[{cfg}] Q={s['Q']} N={N}: G relL2 {max(errs):.2e}, V_eff rel {abs(float(v[0]) - vo) / abs(vo):.2e}")
+    assert max(errs) < TOL_G
+    assert abs(float(v[0]) - vo) < TOL_V * abs(vo)
+
+
 @pytest.mark.parametrize("name,N", [("cfg1", 4), ("cfg2", 4)])
 def test_newton3_mode(name, N, mop, ctx):
     """Newton's-third-law variant (atomics) gives the same gradient."""
