@@ -54,8 +54,11 @@
 
 namespace mop {
 
-// Ring fields (one LDS array [field][entry] per wave; ints stored as float bits).  F_K
-// holds the packed word 16 * exclusion key + LJ type of the system's key table.
+// Ring of j-atoms, one per wave in LDS (ints stored as float bits; the key word is the
+// packed 16 * exclusion key + LJ type of the system's key table).  Full-shell kernels keep
+// entries as float4 {x, y, z, q} followed by float4 {key, v_x, v_y, v_z} (Hessian) or a
+// float {key} (force), so a step reads a j-atom with one or two 16-byte loads.  The
+// Newton-3 kernels keep one array per field [field][entry], F_* below.
 constexpr int F_X = 0, F_Y = 1, F_Z = 2, F_Q = 3, F_K = 4, F_S = 5, F_J = 6;
 
 // Table entries per type pair in LDS, 16 bytes apart: the force kernels keep
@@ -404,6 +407,7 @@ __global__ void __launch_bounds__(64 * PW, EL == 1 ? 4 : 1) k_pair(const SegDev*
     int wp = 0, rp = 0;  // ring write / read counters (uniform); rp stays a multiple of 64
 
     float* ring = s_ring + wave * NF * RING;
+    float4* ring4 = reinterpret_cast<float4*>(ring);
     int* clist = s_cl + wave * CLIST;
 
     // neighbour lists (full-shell kernels): the force pass records the slots that pass
@@ -466,18 +470,39 @@ __global__ void __launch_bounds__(64 * PW, EL == 1 ? 4 : 1) k_pair(const SegDev*
     auto eval_t = [&]<bool EX, bool WE, bool FULL>(int base, int count)
                       __attribute__((always_inline)) {
         float* rb = ring + (base & (RING - 1)) + jslot;
+        const int e0 = (base & (RING - 1)) + jslot;
         const int nsteps = FULL ? 8 : (count + 7) >> 3;
 #pragma unroll
         for (int s = 0; s < nsteps; ++s) {
             const int o = s * 8;
-            const float jx = rb[F_X * RING + o], jy = rb[F_Y * RING + o], jz = rb[F_Z * RING + o];
-            const float qj = rb[F_Q * RING + o];
-            const uint32_t kj = __float_as_uint(rb[F_K * RING + o]);
-            float vjx = 0.f, vjy = 0.f, vjz = 0.f;
-            if (MODE == 1) {
-                vjx = rb[FV * RING + o];
-                vjy = rb[(FV + 1) * RING + o];
-                vjz = rb[(FV + 2) * RING + o];
+            float jx, jy, jz, qj, vjx = 0.f, vjy = 0.f, vjz = 0.f;
+            uint32_t kj;
+            if (N3) {
+                jx = rb[F_X * RING + o];
+                jy = rb[F_Y * RING + o];
+                jz = rb[F_Z * RING + o];
+                qj = rb[F_Q * RING + o];
+                kj = __float_as_uint(rb[F_K * RING + o]);
+                if (MODE == 1) {
+                    vjx = rb[FV * RING + o];
+                    vjy = rb[(FV + 1) * RING + o];
+                    vjz = rb[(FV + 2) * RING + o];
+                }
+            } else {
+                const float4 a = ring4[e0 + o];
+                jx = a.x;
+                jy = a.y;
+                jz = a.z;
+                qj = a.w;
+                if (MODE == 1) {
+                    const float4 w = ring4[RING + e0 + o];
+                    kj = __float_as_uint(w.x);
+                    vjx = w.y;
+                    vjy = w.z;
+                    vjz = w.w;
+                } else {
+                    kj = __float_as_uint(ring[4 * RING + e0 + o]);
+                }
             }
             const bool valid = FULL || o + jslot < count;
             // Entries past the count of a partial chunk may hold anything (never written
@@ -584,22 +609,27 @@ __global__ void __launch_bounds__(64 * PW, EL == 1 ? 4 : 1) k_pair(const SegDev*
             wave_sync();  // previous reads of the ring are done before it is overwritten
             if (pass) {
                 if (rec && wp + off < lcap) nl[wp + off] = slot;
-                float* re = ring + ((wp + off) & (RING - 1));
-                re[F_X * RING] = jx;
-                re[F_Y * RING] = jy;
-                re[F_Z * RING] = jz;
-                re[F_Q * RING] = QSC * jq;
-                re[F_K * RING] = __int_as_float(jk);
+                const int e = (wp + off) & (RING - 1);
                 if (N3) {
+                    float* re = ring + e;
+                    re[F_X * RING] = jx;
+                    re[F_Y * RING] = jy;
+                    re[F_Z * RING] = jz;
+                    re[F_Q * RING] = QSC * jq;
+                    re[F_K * RING] = __int_as_float(jk);
                     re[F_S * RING] = __int_as_float(slot);
                     re[(F_J + 0) * RING] = 0.0f;
                     re[(F_J + 1) * RING] = 0.0f;
                     re[(F_J + 2) * RING] = 0.0f;
-                }
-                if (MODE == 1) {
-                    re[FV * RING] = jv.x;
-                    re[(FV + 1) * RING] = jv.y;
-                    re[(FV + 2) * RING] = jv.z;
+                    if (MODE == 1) {
+                        re[FV * RING] = jv.x;
+                        re[(FV + 1) * RING] = jv.y;
+                        re[(FV + 2) * RING] = jv.z;
+                    }
+                } else {
+                    ring4[e] = make_float4(jx, jy, jz, QSC * jq);
+                    if (MODE == 1) ring4[RING + e] = make_float4(__int_as_float(jk), jv.x, jv.y, jv.z);
+                    else ring[4 * RING + e] = __int_as_float(jk);
                 }
             }
             wp += __popcll(m);
@@ -640,16 +670,9 @@ __global__ void __launch_bounds__(64 * PW, EL == 1 ? 4 : 1) k_pair(const SegDev*
                 jz = (float)(int)(uj.z - ucz) * sz;
             }
             wave_sync();  // the previous chunk's reads of the ring are done
-            if (lane < n) {
-                float* re = ring + lane;
-                re[F_X * RING] = jx;
-                re[F_Y * RING] = jy;
-                re[F_Z * RING] = jz;
-                re[F_Q * RING] = QSC * __uint_as_float(uj.w);
-                re[F_K * RING] = __int_as_float(mj.x);
-                re[FV * RING] = jv.x;
-                re[(FV + 1) * RING] = jv.y;
-                re[(FV + 2) * RING] = jv.z;
+            if (MODE == 1 && !N3 && lane < n) {  // full-shell Hessian kernels only
+                ring4[lane] = make_float4(jx, jy, jz, QSC * __uint_as_float(uj.w));
+                ring4[RING + lane] = make_float4(__int_as_float(mj.x), jv.x, jv.y, jv.z);
             }
             wave_sync();
             if (n == 64) eval.template operator()<true>(0, 64);
