@@ -292,7 +292,7 @@ def bench_pmd(args, mop, ctx, plan, system, Rt, ms_grad, log):
 def bench_pme(args, mop, ctx, system, R, ms_rf, npairs, log):
     """The same path with particle-mesh Ewald electrostatics, the paper's own setting
     (Appendix A.1): Ewald real-space pair kernels at the same cut-off, B-spline order 4
-    on a grid of at most 0.12 nm per point, rocFFT in FP64.  Reports ms per veff_grad
+    on a grid of at most 0.12 nm per point, rocFFT (FP64 force passes, FP32 Hessian pass).  Reports ms per veff_grad
     (eager and graph), the phase split and the cost relative to reaction field."""
     import torch
     import workloads as W

@@ -173,7 +173,9 @@ int mop_system_pme_info(mop_system sys, int32_t grid[3], double* beta);
 
 /* Plan for paths of up to `max_beads` beads of one system (also the maximum B of
  * bead_forces / bead_hvp).  opts may be NULL.  Allocates device memory; for a PME
- * system also creates the batched rocFFT plans (max_beads grids per transform).
+ * system also creates the batched rocFFT plans (max_beads grids per transform; double
+ * precision for the charge grids, single precision for the dipole grids of the Hessian
+ * pass).
  * MOP_EINVAL for MOP_PLAN_NEWTON3 with a PME system.  A PME plan's transforms keep
  * host-side state (stream and work-buffer bindings): do not call one plan from several
  * host threads at once. */

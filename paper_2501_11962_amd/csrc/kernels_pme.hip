@@ -31,6 +31,8 @@
 // All PME arithmetic is FP64.  The FFTs run in rocFFT (host side, mop_api.hip).
 #include <algorithm>
 
+#include <type_traits>
+
 #include "device_common.h"
 #include "launch.h"
 
@@ -385,13 +387,15 @@ __global__ void __launch_bounds__(PME_BLOCK) k_pme_spread(const SegDev* __restri
         flush(ncand);
     }
     __syncthreads();
+    // charges: FP64 grid; dipoles (Hessian pass, FP32 transforms): FP32 grid
     const size_t Kt = (size_t)s.Kg[0] * s.Kg[1] * s.Kg[2];
-    double* gr = wsp<double>(ws, sg.o_pgr) + (size_t)b * Kt;
+    using G = typename std::conditional<KIND == 0, double, float>::type;
+    G* gr = wsp<G>(ws, sg.o_pgr) + (size_t)b * Kt;
     const double inv = 1.0 / scale;
     for (int k = threadIdx.x; k < npts; k += PME_BLOCK) {
         const int kz = k % ez, ky = (k / ez) % ey, kx = k / (ez * ey);
         const size_t g = ((size_t)(lo[0] + kx) * s.Kg[1] + (lo[1] + ky)) * s.Kg[2] + lo[2] + kz;
-        gr[g] = b < nb ? (double)(long long)acc[k] * inv : 0.0;
+        gr[g] = b < nb ? (G)((double)(long long)acc[k] * inv) : (G)0;
     }
 }
 
@@ -427,8 +431,28 @@ __global__ void __launch_bounds__(PME_BLOCK) k_pme_solve(const SegDev* __restric
     }
 }
 
+// The same for the dipole grid of the Hessian pass, in FP32 (no energy).
+__global__ void __launch_bounds__(PME_BLOCK) k_pme_solve32(const SegDev* __restrict__ segs, int nb,
+                                                           char* ws) {
+    const SegDev& sg = segs[0];
+    const SysDev& s = sg.s;
+    const int b = blockIdx.x / s.nsb;
+    const int blk = blockIdx.x - b * s.nsb;
+    if (b >= nb) return;
+    const size_t Kc = (size_t)s.Kg[0] * s.Kg[1] * s.Kzh;
+    const size_t m = (size_t)blk * PME_BLOCK + threadIdx.x;
+    if (m < Kc) {
+        float2* c = wsp<float2>(ws, sg.o_pgc) + (size_t)b * Kc + m;
+        const float ph = (float)s.phihat[m];
+        float2 v = *c;
+        v.x *= ph;
+        v.y *= ph;
+        *c = v;
+    }
+}
+
 // KIND 0: forces from phi (pphi, or pgr for displaced configurations); KIND 1: H v
-// from pphi and the dipole potential in pgr.  outsel 0, 1, 2: added to the float4 pair
+// from pphi and the dipole potential in pgr (FP32).  outsel 0, 1, 2: added to the float4 pair
 // output f32, hv32, f32m; outsel 3, 4: written to the FP64 buffer frec, hrec.
 template <int P, int KIND>
 __global__ void __launch_bounds__(EWB) k_pme_gather(const SegDev* __restrict__ segs, int nb,
@@ -456,7 +480,7 @@ __global__ void __launch_bounds__(EWB) k_pme_gather(const SegDev* __restrict__ s
     const size_t Kt = (size_t)s.Kg[0] * s.Kg[1] * s.Kg[2];
     const double* phi = wsp<const double>(ws, (KIND == 0 && use_pgr) ? sg.o_pgr : sg.o_pphi) +
                         (size_t)b * Kt;
-    const double* dphi = wsp<const double>(ws, sg.o_pgr) + (size_t)b * Kt;
+    const float* dphi = wsp<const float>(ws, sg.o_pgr) + (size_t)b * Kt;
     double vx = 0.0, vy = 0.0, vz = 0.0;
     if (KIND == 1) {
         const double* v = V + ((size_t)b * s.Q + i) * 3;
@@ -483,7 +507,7 @@ __global__ void __launch_bounds__(EWB) k_pme_gather(const SegDev* __restrict__ s
                 St = fma(p, tz[f], St);
                 Sd = fma(p, dz[f], Sd);
                 if (KIND == 1) {
-                    const double q = dphi[row + iz[f]];
+                    const double q = (double)dphi[row + iz[f]];
                     Sh = fma(p, hz[f], Sh);
                     Tt = fma(q, tz[f], Tt);
                     Td = fma(q, dz[f], Td);
@@ -611,6 +635,10 @@ void run_pme_spread(const SegDev* dsegs, const SegDev& h, int nb, int nbatch, ch
 void run_pme_solve(const SegDev* dsegs, const SegDev& h, int nb, char* ws, int want_e,
                    hipStream_t st) {
     hipLaunchKernelGGL(k_pme_solve, dim3(nb * h.s.nsb), dim3(PME_BLOCK), 0, st, dsegs, nb, ws, want_e);
+}
+
+void run_pme_solve32(const SegDev* dsegs, const SegDev& h, int nb, char* ws, hipStream_t st) {
+    hipLaunchKernelGGL(k_pme_solve32, dim3(nb * h.s.nsb), dim3(PME_BLOCK), 0, st, dsegs, nb, ws);
 }
 
 void run_pme_gather(const SegDev* dsegs, const SegDev& h, int nb, char* ws, const double* R,

@@ -57,8 +57,10 @@ void run_pmd_post(const SegDev* dsegs, const SegDev* hsegs, const Launch& base, 
 // Particle-mesh Ewald (single-path launches; nb pair beads).  kind 0: charges / forces,
 // kind 1: dipoles q v / Hessian-vector product.  fdsign != 0 displaces R by fdsign * eps d
 // (finite-difference term).  run_pme_sort orders the atoms by grid tile (needed by the
-// spread and gather of the same configuration); run_pme_spread writes the FP64 real grid
-// of beads < nb and zeros for beads nb .. nbatch-1 of the FFT batch.
+// spread and gather of the same configuration); run_pme_spread writes the real grid of
+// beads < nb and zeros for beads nb .. nbatch-1 of the FFT batch: FP64 for kind 0, FP32
+// for kind 1 (the Hessian pass transforms in single precision; run_pme_solve32 is its
+// solve, and the kind-1 gather reads that FP32 potential).
 void run_pme_sort(const SegDev* dsegs, const SegDev& h, int nb, char* ws, const double* R,
                   int fdsign, double fdh, hipStream_t st);
 void run_pme_spread(const SegDev* dsegs, const SegDev& h, int nb, int nbatch, char* ws,
@@ -66,6 +68,7 @@ void run_pme_spread(const SegDev* dsegs, const SegDev& h, int nb, int nbatch, ch
                     hipStream_t st);
 void run_pme_solve(const SegDev* dsegs, const SegDev& h, int nb, char* ws, int want_e,
                    hipStream_t st);
+void run_pme_solve32(const SegDev* dsegs, const SegDev& h, int nb, char* ws, hipStream_t st);
 // outsel: added to 0 f32, 1 hv32, 2 f32m (float4); written to 3 frec, 4 hrec (FP64);
 // use_pgr: kind-0 potential read from pgr instead of pphi.
 void run_pme_gather(const SegDev* dsegs, const SegDev& h, int nb, char* ws, const double* R,

@@ -33,7 +33,8 @@ T* wsp_host(char* ws, size_t off) {
 
 // Batched double-precision 3-D real FFTs of one PME grid shape (rocFFT).
 struct PmeFft {
-    rocfft_plan fwd = nullptr, bwd = nullptr;
+    rocfft_plan fwd = nullptr, bwd = nullptr;      // FP64: charges (force passes)
+    rocfft_plan fwd32 = nullptr, bwd32 = nullptr;  // FP32: dipoles (Hessian pass)
     rocfft_execution_info info = nullptr;
     size_t work = 0;
 };
@@ -625,12 +626,15 @@ void mop_system_destroy(mop_system sys) {
 static void destroy_fft(PmeFft& f) {
     if (f.fwd) (void)rocfft_plan_destroy(f.fwd);
     if (f.bwd) (void)rocfft_plan_destroy(f.bwd);
+    if (f.fwd32) (void)rocfft_plan_destroy(f.fwd32);
+    if (f.bwd32) (void)rocfft_plan_destroy(f.bwd32);
     if (f.info) (void)rocfft_execution_info_destroy(f.info);
     f = PmeFft();
 }
 
-// Out-of-place double-precision real <-> half-complex 3-D transforms of `batch` grids
-// K0 x K1 x K2 (K2 fastest), real grids packed K apart, spectra Kc apart.
+// Out-of-place real <-> half-complex 3-D transforms of `batch` grids K0 x K1 x K2 (K2
+// fastest), real grids packed K apart, spectra Kc apart: in double precision for the
+// charge grids, in single precision for the dipole grids of the Hessian pass.
 static int make_fft(PmeFft& f, const int K[3], int batch) {
     static bool ready = false;
     if (!ready) {
@@ -657,9 +661,17 @@ static int make_fft(PmeFft& f, const int K[3], int batch) {
     ok = ok && rocfft_plan_create(&f.bwd, rocfft_placement_notinplace,
                                   rocfft_transform_type_real_inverse, rocfft_precision_double, 3,
                                   len, batch, db) == rocfft_status_success;
-    size_t w1 = 0, w2 = 0;
+    ok = ok && rocfft_plan_create(&f.fwd32, rocfft_placement_notinplace,
+                                  rocfft_transform_type_real_forward, rocfft_precision_single, 3,
+                                  len, batch, df) == rocfft_status_success;
+    ok = ok && rocfft_plan_create(&f.bwd32, rocfft_placement_notinplace,
+                                  rocfft_transform_type_real_inverse, rocfft_precision_single, 3,
+                                  len, batch, db) == rocfft_status_success;
+    size_t w1 = 0, w2 = 0, w3 = 0, w4 = 0;
     ok = ok && rocfft_plan_get_work_buffer_size(f.fwd, &w1) == rocfft_status_success &&
-         rocfft_plan_get_work_buffer_size(f.bwd, &w2) == rocfft_status_success;
+         rocfft_plan_get_work_buffer_size(f.bwd, &w2) == rocfft_status_success &&
+         rocfft_plan_get_work_buffer_size(f.fwd32, &w3) == rocfft_status_success &&
+         rocfft_plan_get_work_buffer_size(f.bwd32, &w4) == rocfft_status_success;
     ok = ok && rocfft_execution_info_create(&f.info) == rocfft_status_success;
     if (df) (void)rocfft_plan_description_destroy(df);
     if (db) (void)rocfft_plan_description_destroy(db);
@@ -667,20 +679,21 @@ static int make_fft(PmeFft& f, const int K[3], int batch) {
         destroy_fft(f);
         return MOP_EHIP;
     }
-    f.work = std::max(w1, w2);
+    f.work = std::max(std::max(w1, w2), std::max(w3, w4));
     return MOP_OK;
 }
 
 // One batched transform on `st` (the work buffer lives in the caller's workspace).
 static void run_fft(const mop_plan_s* pl, bool forward, void* in, void* out, void* work,
-                    hipStream_t st) {
+                    hipStream_t st, bool single = false) {
     const PmeFft& f = pl->fft;
     bool ok = rocfft_execution_info_set_stream(f.info, st) == rocfft_status_success;
     if (f.work)
         ok = ok && rocfft_execution_info_set_work_buffer(f.info, work, f.work) == rocfft_status_success;
     void* ib[1] = {in};
     void* ob[1] = {out};
-    ok = ok && rocfft_execute(forward ? f.fwd : f.bwd, ib, ob, f.info) == rocfft_status_success;
+    const rocfft_plan plan = single ? (forward ? f.fwd32 : f.bwd32) : (forward ? f.fwd : f.bwd);
+    ok = ok && rocfft_execute(plan, ib, ob, f.info) == rocfft_status_success;
     if (!ok) pl->fft_failed = true;
 }
 
@@ -827,9 +840,9 @@ static void pme_hvp(const mop_plan_s* pl, int nb, const CallPtrs& cp, const doub
     const SegDev& h = pl->hseg;
     char* ws = cp.ws;
     run_pme_spread(pl->dseg, h, nb, h.maxb, ws, cp.R, V, 1, 0, 0.0, st);
-    run_fft(pl, true, ws + h.o_pgr, ws + h.o_pgc, ws + h.o_pfw, st);
-    run_pme_solve(pl->dseg, h, nb, ws, 0, st);
-    run_fft(pl, false, ws + h.o_pgc, ws + h.o_pgr, ws + h.o_pfw, st);
+    run_fft(pl, true, ws + h.o_pgr, ws + h.o_pgc, ws + h.o_pfw, st, true);
+    run_pme_solve32(pl->dseg, h, nb, ws, st);
+    run_fft(pl, false, ws + h.o_pgc, ws + h.o_pgr, ws + h.o_pfw, st, true);
     run_pme_gather(pl->dseg, h, nb, ws, cp.R, V, 1, 0, 0.0, 4, 0, st);
 }
 
