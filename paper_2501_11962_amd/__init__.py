@@ -158,6 +158,16 @@ def _dev_tensor(t, dtype, shape=None):
     return t
 
 
+def _beads(plan, R):
+    """R must be (B, Q, 3) float64 on the device, Q the plan's atom count: the library
+    takes only the bead count and reads B * Q * 3 values."""
+    torch = _torch()
+    _dev_tensor(R, torch.float64)
+    if R.dim() != 3 or R.shape[0] < 1 or R.shape[1] != plan.Q or R.shape[2] != 3:
+        raise ValueError(f"expected shape (beads, {plan.Q}, 3), got {tuple(R.shape)}")
+    return R
+
+
 class _HostArrays:
     """Keeps the host arrays of a descriptor alive."""
 
@@ -291,12 +301,15 @@ class Plan:
 def bead_forces(plan, R, F=None, U=None, want_energy=True):
     """F = -grad U per configuration: R (B, Q, 3) float64 -> F (B, Q, 3) float32, U (B,)."""
     torch = _torch()
-    _dev_tensor(R, torch.float64)
+    _beads(plan, R)
     B = R.shape[0]
     if F is None:
         F = torch.empty((B, plan.Q, 3), dtype=torch.float32, device=R.device)
+    _dev_tensor(F, torch.float32, (B, plan.Q, 3))
     if U is None and want_energy:
         U = torch.empty(B, dtype=torch.float64, device=R.device)
+    if U is not None:
+        _dev_tensor(U, torch.float64, (B,))
     _check(lib().bead_forces(plan.h, _ptr(R), B, _ptr(F), _ptr(U), _ptr(plan.ws)), "bead_forces")
     return F, U
 
@@ -304,11 +317,12 @@ def bead_forces(plan, R, F=None, U=None, want_energy=True):
 def bead_hvp(plan, R, V, HV=None):
     """H(R^b) V^b: R, V (B, Q, 3) float64 -> (B, Q, 3) float32."""
     torch = _torch()
-    _dev_tensor(R, torch.float64)
+    _beads(plan, R)
     _dev_tensor(V, torch.float64, R.shape)
     B = R.shape[0]
     if HV is None:
         HV = torch.empty((B, plan.Q, 3), dtype=torch.float32, device=R.device)
+    _dev_tensor(HV, torch.float32, (B, plan.Q, 3))
     _check(lib().bead_hvp(plan.h, _ptr(R), _ptr(V), B, _ptr(HV), _ptr(plan.ws)), "bead_hvp")
     return HV
 
@@ -316,7 +330,7 @@ def bead_hvp(plan, R, V, HV=None):
 def veff_energy(plan, R):
     """(V_eff, U(R^1), spring energy) as a (3,) float64 CUDA tensor."""
     torch = _torch()
-    _dev_tensor(R, torch.float64)
+    _beads(plan, R)
     out = torch.empty(3, dtype=torch.float64, device=R.device)
     p = out.data_ptr()
     _check(lib().veff_energy(plan.h, _ptr(R), R.shape[0], C.c_void_p(p), C.c_void_p(p + 8),
@@ -328,11 +342,13 @@ def veff_grad(plan, R, mode=0, fd_h=1e-4, G=None, veff=None):
     """(G, V_eff): G (N, Q, 3) float64 = grad V_eff; mode 0 exact HVP, 1 finite differences
     (displaced configurations re-binned), 2 finite differences on the binning of R."""
     torch = _torch()
-    _dev_tensor(R, torch.float64)
+    _beads(plan, R)
     if G is None:
         G = torch.empty_like(R)
     if veff is None:
         veff = torch.empty(1, dtype=torch.float64, device=R.device)
+    _dev_tensor(G, torch.float64, R.shape)
+    _dev_tensor(veff, torch.float64, (1,))
     _check(lib().veff_grad(plan.h, _ptr(R), R.shape[0], _ptr(G), _ptr(veff), int(mode),
                            float(fd_h), _ptr(plan.ws)), "veff_grad")
     return G, veff
@@ -357,7 +373,7 @@ class Bias:
     def apply(self, R, G=None, deposit=False):
         """Adds grad V_bias to G (if given); returns a CUDA tensor {V_bias, S}."""
         torch = _torch()
-        _dev_tensor(R, torch.float64)
+        _beads(self.plan, R)
         if G is not None:
             _dev_tensor(G, torch.float64, R.shape)
         out = torch.empty(2, dtype=torch.float64, device=R.device)
@@ -391,12 +407,12 @@ def pmd_step(plan, R, V, G, tau, nsteps=1, gamma=0.0, kT=0.0, seed=0, step0=0,
     total potential at R on entry and holds that of the final R on exit.  Returns energies
     (nsteps, 4) float64 {V_eff, kinetic, V_bias, S} after each step (a CUDA tensor)."""
     torch = _torch()
-    for t in (R, V, G):
-        _dev_tensor(t, torch.float64)
-    if not (V.shape == R.shape and G.shape == R.shape):
-        raise ValueError("R, V and G must have the same shape")
+    _beads(plan, R)
+    for t in (V, G):
+        _dev_tensor(t, torch.float64, R.shape)
     if energies is None:
         energies = torch.empty((int(nsteps), 4), dtype=torch.float64, device=R.device)
+    _dev_tensor(energies, torch.float64, (int(nsteps), 4))
     prm = _PmdParams(float(tau), float(gamma), float(kT), int(seed) & (2 ** 64 - 1))
     _check(lib().pmd_step(plan.h, bias.h if bias is not None else None, _ptr(R), _ptr(V),
                           _ptr(G), R.shape[0], C.byref(prm), int(step0), int(nsteps),
@@ -407,11 +423,13 @@ def pmd_step(plan, R, V, G, tau, nsteps=1, gamma=0.0, kT=0.0, seed=0, step0=0,
 def veff_grad_timed(plan, R, mode=0, fd_h=1e-4, G=None, veff=None):
     """veff_grad with HIP events between phases; returns (G, veff, {phase: ms})."""
     torch = _torch()
-    _dev_tensor(R, torch.float64)
+    _beads(plan, R)
     if G is None:
         G = torch.empty_like(R)
     if veff is None:
         veff = torch.empty(1, dtype=torch.float64, device=R.device)
+    _dev_tensor(G, torch.float64, R.shape)
+    _dev_tensor(veff, torch.float64, (1,))
     ms = (C.c_float * len(PHASES))()
     _check(lib().veff_grad_timed(plan.h, _ptr(R), R.shape[0], _ptr(G), _ptr(veff), int(mode),
                                  float(fd_h), _ptr(plan.ws), ms), "veff_grad_timed")
@@ -449,11 +467,13 @@ class Batch:
 
     def veff_grad(self, Rflat, mode=0, fd_h=1e-4, G=None, veff=None):
         torch = _torch()
-        _dev_tensor(Rflat, torch.float64)
+        _dev_tensor(Rflat, torch.float64, (int(self.offsets[-1]),))
         if G is None:
             G = torch.empty_like(Rflat)
         if veff is None:
             veff = torch.empty(self.P, dtype=torch.float64, device=Rflat.device)
+        _dev_tensor(G, torch.float64, Rflat.shape)
+        _dev_tensor(veff, torch.float64, (self.P,))
         _check(lib().mop_batch_veff_grad(self.h, _ptr(Rflat), _ptr(G), _ptr(veff), int(mode),
                                          float(fd_h), _ptr(self.ws)), "mop_batch_veff_grad")
         return G, veff

@@ -158,6 +158,56 @@ def test_single_bead_and_single_atom(mop, ctx):
     assert abs(float(v1.cpu()[0]) - vo) < 1e-12 * abs(vo)
 
 
+@pytest.mark.parametrize("pme", [False, True])
+def test_plan_capacity_above_the_path_length(pme, mop, ctx):
+    """A plan made for more beads than the path gives the same gradient as one made for
+    exactly its beads (bit for bit with reaction field; PME transforms run over the plan's
+    whole bead capacity, so there the batch size may change rounding); a path longer than
+    the plan is refused with MOP_ESIZE (-7)."""
+    s = W.water_box(1002, seed=9, rc=1.0)
+    if pme:
+        s = W.with_pme(s)
+    R, _, _ = W.random_walk_path(s, 5, 43)
+    sysm = mop.System(ctx, s)
+    G5, v5 = (x.cpu().numpy() for x in mop.veff_grad(mop.Plan(sysm, 5), cuda(R)))
+    big = mop.Plan(sysm, 9)
+    G9, v9 = (x.cpu().numpy() for x in mop.veff_grad(big, cuda(R)))
+    assert big.status() == 0
+    if pme:
+        assert rel(G9, G5) < 1e-12 and abs(v9[0] - v5[0]) < 1e-12 * abs(v5[0])
+    else:
+        assert np.array_equal(G9, G5) and np.array_equal(v9, v5)
+    R12, _, _ = W.random_walk_path(s, 12, 44)
+    with pytest.raises(mop.MopError) as e:
+        mop.veff_grad(big, cuda(R12))
+    assert e.value.code == -7
+
+
+def test_binding_checks_shapes_before_any_launch(mop, ctx):
+    """The C calls take only a bead count and read B * Q * 3 values, so the binding refuses
+    tensors whose shape does not match the plan before anything reaches the device."""
+    import torch
+    s = W.cfg1()
+    R, _, _ = W.random_walk_path(s, 3, 2, 0.005)
+    plan = mop.Plan(mop.System(ctx, s), 3)
+    Rt = cuda(R)
+    bad = [cuda(R[:, :-1]), cuda(R[..., :2]), cuda(R[0]), cuda(R.reshape(3, -1))]
+    for B in bad:
+        for call in (lambda x: mop.veff_grad(plan, x), lambda x: mop.veff_energy(plan, x),
+                     lambda x: mop.bead_forces(plan, x), lambda x: mop.bead_hvp(plan, x, x)):
+            with pytest.raises(ValueError):
+                call(B)
+    with pytest.raises(ValueError):
+        mop.veff_grad(plan, Rt, G=torch.empty((2, s["Q"], 3), dtype=torch.float64, device="cuda"))
+    with pytest.raises(TypeError):
+        mop.bead_forces(plan, Rt, F=torch.empty((3, s["Q"], 3), dtype=torch.float64, device="cuda"))
+    bt = mop.Batch([plan], [3])
+    with pytest.raises(ValueError):
+        bt.veff_grad(Rt.reshape(-1)[:-3].contiguous())
+    G, v = mop.veff_grad(plan, Rt)          # the right shapes still work
+    assert plan.status() == 0 and torch.isfinite(G).all()
+
+
 def test_unwrapped_coordinates(mop, ctx):
     s = W.cfg2()
     R, _, _ = W.random_walk_path(s, 4, 5)
