@@ -108,10 +108,9 @@ def executed_from_profiles(workload):
     per compute-unit cycle, from the committed summary if it matches the kernel source."""
     kv = profile_summary(f"valu_pair_{workload}.md")
     try:
-        return None if kv is None else {k: float(kv[k]) for k in (
-            "hvp_executed_flops_per_launch", "force_executed_flops_per_launch",
-            "hvp_valu_per_cu_cycle", "force_valu_per_cu_cycle")}
-    except (KeyError, ValueError):
+        return None if kv is None else {k: float(v) for k, v in kv.items()
+                                        if k.endswith(("_per_launch", "_per_cu_cycle"))}
+    except ValueError:
         return None
 
 
@@ -366,6 +365,15 @@ def bench_pme(args, mop, ctx, system, R, ms_rf, npairs, log):
                              hvp=round(phases_1s["pme_hvp"], 4)),
                 mesh_wait_at_join_ms=dict(force=round(phases["pme_force"], 4),
                                           hvp=round(phases["pme_hvp"], 4)))
+    ex = executed_from_profiles(args.config)
+    if ex and "ewald_hvp_executed_flops_per_launch" in ex:
+        # counted FP32 work of the Ewald kernels over their one-stream launch times
+        e_h = ex["ewald_hvp_executed_flops_per_launch"] / t_hvp / 1e12
+        roof["executed"] = dict(tflops=round(e_h, 3), frac=round(e_h / PEAK_FP32_TFLOPS, 4),
+                                valu_per_cu_cycle=ex.get("ewald_hvp_valu_per_cu_cycle"),
+                                source=f"profiles/valu_pair_{args.config}.md")
+        roof["force_kernel"]["executed_tflops"] = round(
+            ex["ewald_force_executed_flops_per_launch"] / t_force / 1e12, 3)
     out = dict(workload=f"{system['name']} with particle-mesh Ewald: grid {grid[0]}x{grid[1]}x"
                         f"{grid[2]}, order {s['pme_order']}, beta {beta:.4f} / nm, "
                         f"real-space cut-off {s['rc']} nm",
@@ -564,7 +572,7 @@ def main():
                                   launch_ms=round(phases["force"], 4)),
                 whole_step_tflops=round((flops_hvp + flops_force) / (ms * 1e-3) / 1e12, 3))
     ex = executed_from_profiles(args.config)
-    if ex:
+    if ex and "hvp_executed_flops_per_launch" in ex:
         # executed work (both sides of each pair, combinations beyond the cutoff, search
         # and bookkeeping instructions) per launch, over this run's launch times
         roof["executed"] = dict(
