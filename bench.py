@@ -31,9 +31,14 @@ METRIC = "veff_grad atom·beads/s, analytic HVP vs finite-diff HVP, 1 MI355X"
 PEAK_FP32_TFLOPS = 157.3      # MI355X FP32 vector (published)
 PEAK_HBM_GBS = 8000.0
 # Algorithmic FLOPs per unique within-cutoff pair (FMA = 2, rsqrt = 1, others 1),
-# counted from the pair formulas with Newton's third law (each pair once).
-FLOP_FORCE_PAIR = 34
-FLOP_HVP_PAIR = 60
+# counted term by term from the pair formulas, each pair once (Newton's third law: the
+# partner's update is counted as well):
+#   force  d 3, r^2 5, rsqrt 1, r^-2 r^-3 r^-6 r^-8 4, q_i q_j 1, C1 2, G6 2, g 6,
+#          g d 3, two 3-vector updates 6                                        = 33
+#   HVP    d 3, r^2 5, rsqrt 1, powers 4, q_i q_j 1, C1 2, G6 2, g 6, h6 2, r^-5 1,
+#          h 7, dv 3, d.dv 5, h d.dv 1, g dv + (h d.dv) d 9, two updates 6      = 58
+FLOP_FORCE_PAIR = 33
+FLOP_HVP_PAIR = 58
 # Ewald real space: the reaction-field terms of g (and h) replaced by erfc/exp terms
 # (erfc as exp(-x^2) times a degree-8 polynomial in 1/(1 + x/2); exp and reciprocal 1 each):
 # g 11 -> 38 flops, h 11 -> 16 flops.
@@ -90,15 +95,34 @@ def profile_summary(name):
 
 
 def traffic_from_profiles(workload):
-    """HBM bytes per launch of the Hessian pair kernel measured by rocprofv3 counters
-    (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter reads for a plain copy of
-    known size), from the committed summary, if it was taken on the current kernel
-    source; else None."""
-    kv = profile_summary(f"traffic_pair_hvp_{workload}.md")
+    """HBM bytes per launch of the force and Hessian pair kernels measured by rocprofv3
+    counters (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter reads for a plain
+    copy of known size), from the committed summary, if it was taken on the current kernel
+    source; else None for each."""
+    kv = profile_summary(f"traffic_pair_{workload}.md") or {}
+    out = {}
+    for k in ("force", "hvp"):
+        try:
+            out[k] = int(float(kv[f"{k}_bytes_per_launch"]))
+        except (KeyError, ValueError):
+            out[k] = None
+    return out
+
+
+def cpu_description():
+    """Model name, family / model / stepping numbers and core count of the host CPU."""
+    info = {}
     try:
-        return int(float(kv["bytes_per_launch"])) if kv else None
-    except (KeyError, ValueError):
-        return None
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if ":" in line:
+                    k, v = line.split(":", 1)
+                    info.setdefault(k.strip(), v.strip())
+    except OSError:
+        pass
+    name = info.get("model name", "unknown")
+    ids = ", ".join(f"{k} {info[k]}" for k in ("cpu family", "model", "stepping") if k in info)
+    return f"{name} ({ids})" if ids else name
 
 
 def executed_from_profiles(workload):
@@ -128,12 +152,7 @@ def cpu_baseline(system, R, beads):
     t1 = time.perf_counter()
     OP.veff_grad(m1, np.ascontiguousarray(R[:2]))
     dt1 = time.perf_counter() - t1
-    model = "unknown"
-    try:
-        with open("/proc/cpuinfo") as f:
-            model = next(l.split(":", 1)[1].strip() for l in f if l.startswith("model name"))
-    except (OSError, StopIteration):
-        pass
+    model = cpu_description()
     # beads 1 .. beads-1 of the sub-path carry the same gradient as in the whole path
     return dict(value=system["Q"] * beads / dt, unit="atom·beads/s", cores=cl.max_threads(),
                 kind="oracle", cpu_model=model, host_cpus=os.cpu_count(),
@@ -146,18 +165,27 @@ def cpu_baseline(system, R, beads):
 
 def bench_batch(args, mop, ctx, log):
     """The uneven batch: 24 independent water paths (Q log-uniform in [1e3, 2e4], N
-    uniform in [16, 128]) in one launch per phase, captured once in a graph.  Aggregate
+    uniform in [16, 128], tethered Brownian beads) in one launch per phase, captured once
+    in a graph.  Aggregate
     atom*beads/s, and each path's gradient of beads 1-2 against the FP64 oracle (C cell
     list) on the first three beads."""
     import torch
     import workloads as W
-    specs = W.cfg5()
-    plans, paths, Rs = [], [], []
-    for s_, N, seed in specs:
-        R, _, _ = W.random_walk_path(s_, N, seed)
+    batch = W.batch_paths()
+    specs = [(s_, R.shape[0], seed) for s_, R, seed in batch]
+    plans, paths, Rs, popts = [], [], [], []
+    tuned = not args.no_autotune
+    if tuned:
+        from paper_2501_11962_amd import autotune as A
+        space = {k: v for k, v in A.SPACE.items() if k != "waves"}   # one launch shape per batch
+    for s_, R, seed in batch:
+        N = R.shape[0]
         Rs.append(R)
-        plans.append(mop.Plan(mop.System(ctx, s_), N))
-        paths.append(torch.from_numpy(R).cuda())
+        Rp = torch.from_numpy(R).cuda()
+        o = A.autotune(ctx, s_, Rp, space=space, cache=args.tune_cache) if tuned else {}
+        popts.append(o)
+        plans.append(mop.Plan(mop.System(ctx, s_), N, **o))
+        paths.append(Rp)
     bt = mop.Batch(plans, [n for _, n, _ in specs])
     Rf = bt.pack(paths)
     G = torch.empty_like(Rf)
@@ -196,15 +224,33 @@ def bench_batch(args, mop, ctx, log):
             ms_graph = e0.elapsed_time(e1) / args.steps
         else:
             log("[bench] batch graph replay differs from the eager call; graph timing skipped")
-    # both timings cover the whole call; report the faster way of issuing it
-    ms = min(ms_eager, ms_graph) if ms_graph is not None else ms_eager
+    ms = ms_graph if ms_graph is not None else ms_eager   # graph replay, as for the headline
+    ms_default = None
+    if tuned:
+        # the same batch with default plans, for the autotuner's gain
+        dplans = [mop.Plan(mop.System(ctx, s_), n) for s_, n, _ in specs]
+        dbt = mop.Batch(dplans, [n for _, n, _ in specs])
+        for _ in range(args.warmup):
+            dbt.veff_grad(Rf, G=G, veff=v)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(args.steps):
+            dbt.veff_grad(Rf, G=G, veff=v)
+        e1.record()
+        torch.cuda.synchronize()
+        ms_default = e0.elapsed_time(e1) / args.steps
+        del dbt, dplans
+        bt.veff_grad(Rf, G=G, veff=v)   # G of the tuned batch again, for the error check
+        torch.cuda.synchronize()
     work = sum(s_["Q"] * n for s_, n, _ in specs)
     out = dict(workload=f"cfg5: {bt.P} water paths, Q {min(s_['Q'] for s_, _, _ in specs)}.."
                         f"{max(s_['Q'] for s_, _, _ in specs)}, N {min(n for _, n, _ in specs)}.."
                         f"{max(n for _, n, _ in specs)}, rc 1.0 nm",
                value=work / (ms * 1e-3), unit="atom·beads/s", ms_per_call=ms,
                ms_eager=ms_eager, ms_graph=ms_graph,
-               graph=ms_graph is not None and ms_graph <= ms_eager, atom_beads=work)
+               graph=ms_graph is not None, atom_beads=work,
+               plan_options=popts if tuned else "default",
+               ms_eager_default_plans=ms_default)
     log(f"[bench] batch: {ms:.3f} ms/call, {out['value']:.3e} atom*beads/s")
     if not args.no_cpu_baseline:
         from oracle import cl
@@ -222,11 +268,11 @@ def bench_batch(args, mop, ctx, log):
 
 def bench_pmd(args, mop, ctx, plan, system, Rt, ms_grad, log):
     """Path dynamics on the same workload: Langevin B A O A B steps (gamma = 250 / ps,
-    300 K) with the metadynamics bias on the end-to-end variable of eq. (8).  The
-    synthetic membrane is not relaxed (it keeps overlapping atoms), so the step is
-    0.01 fs to keep the run finite; the cost of a step does not depend on it.  Groups: one bonded 50-atom chain (ligand-sized) and the atoms within
-    1.2 nm of its first atom (pocket-sized).  Reports ms per step and what the
-    integrator and the bias add to one veff_grad call."""
+    300 K, time step 0.5 fs) with the metadynamics bias on the end-to-end variable of
+    eq. (8), from the relaxed starting structure.  Groups: one bonded 50-atom chain
+    (ligand-sized) and the atoms within 1.2 nm of its first atom (pocket-sized).  Reports
+    ms per step, what the integrator and the bias add to one veff_grad call, and whether
+    the energies stayed finite."""
     import torch
     X = np.asarray(system["x"])
     L = np.asarray(system["box"])
@@ -245,7 +291,7 @@ def bench_pmd(args, mop, ctx, plan, system, Rt, ms_grad, log):
     G, _ = mop.veff_grad(plan, R)
     bias.apply(R, G)
     steps = max(args.steps // 2, 5)
-    tau = 1e-5
+    tau = 5e-4
     mop.pmd_step(plan, R, V, G, tau, 2, 250.0, kT, seed=7, step0=0, bias=bias)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -257,7 +303,7 @@ def bench_pmd(args, mop, ctx, plan, system, Rt, ms_grad, log):
     st = plan.status()
     Q, N = system["Q"], Rt.shape[0]
     out = dict(workload=f"Langevin path dynamics with the end-to-end bias: groups of {len(A)} "
-                        f"and {len(B)} atoms, deposit every 5 steps, tau 0.01 fs",
+                        f"and {len(B)} atoms, deposit every 5 steps, tau {tau * 1e3:g} fs",
                ms_per_step=ms, value=Q * N / (ms * 1e-3), unit="atom·beads/s",
                overhead_vs_veff_grad_ms=ms - ms_grad, steps=steps,
                gaussians=len(bias.history()[0]), device_status=st,
@@ -421,6 +467,10 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-pmd", action="store_true")
     ap.add_argument("--no-pme", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="default plan options instead of the autotuner's choice")
+    ap.add_argument("--tune-cache", default=os.path.join("/tmp", f"mop_autotune_{os.getuid()}.json"),
+                    help="autotuner cache file (JSON)")
     ap.add_argument("--pme-one-stream", action="store_true",
                     help="PME leg: mesh work on the caller's stream (times each kernel alone)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -444,7 +494,18 @@ def main():
     torch.cuda.set_device(dev)
     Rt = torch.from_numpy(R).to(dev)
     ctx = mop.Context()
-    plan = mop.Plan(mop.System(ctx, system), N)
+    tune = None
+    opts = {}
+    if not args.no_autotune:
+        # plan geometry and launch shape chosen on this path (outside the timed region)
+        from paper_2501_11962_amd import autotune as A
+        opts, tinfo = A.autotune(ctx, system, Rt, with_info=True, cache=args.tune_cache,
+                                 log=log)
+        tune = dict(default_ms=tinfo["default_ms"], tuned_ms=tinfo["ms"],
+                    settings_timed=len(tinfo["tried"]), cached=tinfo["cached"])
+        log(f"[bench] autotuned plan options {opts} ({tinfo['ms']:.3f} ms against "
+            f"{tinfo['default_ms']} ms for the default plan)")
+    plan = mop.Plan(mop.System(ctx, system), N, **opts)
     G = torch.empty_like(Rt)
     v = torch.empty(1, dtype=torch.float64, device=dev)
     if args.calib_copy_mib > 0:
@@ -467,19 +528,27 @@ def main():
         raise SystemExit(f"device status {st} after warm-up")
     log(f"[bench] warm-up done, V_eff = {float(v[0]):.6e}")
 
-    # eager timing
+    def timed(fn, steps):
+        """Mean over `steps` back-to-back calls (events bracketing the window, the host
+        synchronised on both sides) and the median of the per-call times (an event between
+        consecutive calls)."""
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+        torch.cuda.synchronize()
+        ev[0].record()
+        for k in range(steps):
+            fn()
+            ev[k + 1].record()
+        torch.cuda.synchronize()
+        per = [ev[k].elapsed_time(ev[k + 1]) for k in range(steps)]
+        return ev[0].elapsed_time(ev[steps]) / steps, float(np.median(per))
+
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record()
-    for _ in range(args.steps):
-        step()
-    e1.record()
-    torch.cuda.synchronize()
-    ms_eager = e0.elapsed_time(e1) / args.steps
-    log(f"[bench] eager: {ms_eager:.3f} ms/step")
+    # eager timing
+    ms_eager, med_eager = timed(step, args.steps)
+    log(f"[bench] eager: {ms_eager:.3f} ms/step (median {med_eager:.3f})")
 
     # the whole call captured once in a graph and replayed
-    ms_graph = None
+    ms_graph = med_graph = None
     if not args.no_graph:
         try:
             g = torch.cuda.CUDAGraph()
@@ -497,19 +566,16 @@ def main():
             if not torch.equal(G, Gref):
                 err = float((G - Gref).norm() / Gref.norm())
                 raise RuntimeError(f"graph replay differs from eager (rel L2 {err:.2e})")
-            torch.cuda.synchronize()
-            e0.record()
-            for _ in range(args.steps):
+            for _ in range(3):
                 g.replay()
-            e1.record()
-            torch.cuda.synchronize()
-            ms_graph = e0.elapsed_time(e1) / args.steps
-            log(f"[bench] graph: {ms_graph:.3f} ms/step")
+            ms_graph, med_graph = timed(g.replay, args.steps)
+            log(f"[bench] graph: {ms_graph:.3f} ms/step (median {med_graph:.3f})")
         except Exception as ex:  # graph capture is optional; eager timing stands
             log(f"[bench] graph capture skipped: {ex}")
             ctx.set_stream()
-    # both timings cover the whole call; report the faster way of issuing it
-    ms = min(ms_eager, ms_graph) if ms_graph is not None else ms_eager
+    # the headline is the graph replay (the whole call captured once, the way a serving
+    # loop issues it); eager launches are reported beside it
+    ms = ms_graph if ms_graph is not None else ms_eager
 
     # per-phase times (HIP events between phases, same stream)
     acc = None
@@ -555,33 +621,42 @@ def main():
             mop.veff_grad(plan, Rt, 1, h, G, v)
             Gfd_head[h] = G[:Ga_head.shape[0]].cpu().numpy()
 
-    # roofline of the dominant kernel
+    # roofline of the pair kernels; the headline fields are those of the one with the
+    # longer launch (the dominant kernel of the step)
     npairs = unique_pairs(system, R[0])
     pair_beads = N - 1
-    flops_hvp = FLOP_HVP_PAIR * npairs * pair_beads
-    flops_force = FLOP_FORCE_PAIR * npairs * pair_beads
-    t_hvp, t_force = phases["hvp"] * 1e-3, phases["force"] * 1e-3
-    ach = flops_hvp / t_hvp / 1e12
     traffic = traffic_from_profiles(args.config)
-    roof = dict(bound="alu", kernel="k_pair<1,4,0,0> (pair Hessian-vector product)",
-                achieved=round(ach, 3), peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
-                frac=round(ach / PEAK_FP32_TFLOPS, 4), traffic=traffic,
-                algorithmic_flops_per_launch=flops_hvp, pairs_per_bead=npairs,
-                launch_ms=round(phases["hvp"], 4),
-                force_kernel=dict(achieved=round(flops_force / t_force / 1e12, 3),
-                                  launch_ms=round(phases["force"], 4)),
-                whole_step_tflops=round((flops_hvp + flops_force) / (ms * 1e-3) / 1e12, 3))
-    ex = executed_from_profiles(args.config)
-    if ex and "hvp_executed_flops_per_launch" in ex:
-        # executed work (both sides of each pair, combinations beyond the cutoff, search
-        # and bookkeeping instructions) per launch, over this run's launch times
-        roof["executed"] = dict(
-            tflops=round(ex["hvp_executed_flops_per_launch"] / t_hvp / 1e12, 3),
-            frac=round(ex["hvp_executed_flops_per_launch"] / t_hvp / 1e12 / PEAK_FP32_TFLOPS, 4),
-            valu_per_cu_cycle=ex["hvp_valu_per_cu_cycle"],
-            source=f"profiles/valu_pair_{args.config}.md")
-        roof["force_kernel"]["executed_tflops"] = round(
-            ex["force_executed_flops_per_launch"] / t_force / 1e12, 3)
+    ex = executed_from_profiles(args.config) or {}
+    kern = {}
+    for k, name, fpp in (("force", "k_pair<0,4,0,0> (pair forces + neighbour-list records)",
+                          FLOP_FORCE_PAIR),
+                         ("hvp", "k_pair<1,4,0,0> (pair Hessian-vector product, list replay)",
+                          FLOP_HVP_PAIR)):
+        t = phases[k] * 1e-3
+        flops = fpp * npairs * pair_beads
+        ach = flops / t / 1e12
+        kk = dict(kernel=name, achieved=round(ach, 3), frac=round(ach / PEAK_FP32_TFLOPS, 4),
+                  launch_ms=round(phases[k], 4), flop_per_pair=fpp,
+                  algorithmic_flops_per_launch=flops, traffic=traffic[k])
+        if traffic[k] is not None:
+            gbs = traffic[k] / t / 1e9
+            kk.update(hbm_gbs=round(gbs, 1), hbm_frac=round(gbs / PEAK_HBM_GBS, 4))
+        if f"{k}_executed_flops_per_launch" in ex:
+            # executed work (both sides of each pair, combinations beyond the cutoff, search
+            # and bookkeeping instructions) per launch, over this run's launch time
+            e_t = ex[f"{k}_executed_flops_per_launch"] / t / 1e12
+            kk["executed"] = dict(tflops=round(e_t, 3), frac=round(e_t / PEAK_FP32_TFLOPS, 4),
+                                  valu_per_cu_cycle=ex.get(f"{k}_valu_per_cu_cycle"),
+                                  source=f"profiles/valu_pair_{args.config}.md")
+        kern[k] = kk
+    dom = max(kern, key=lambda k: kern[k]["launch_ms"])
+    roof = dict(bound="alu", peak=PEAK_FP32_TFLOPS, unit="TFLOP/s", **kern[dom],
+                dominant=dom, pairs_per_bead=npairs, pair_beads_per_launch=pair_beads,
+                hbm_peak_gbs=PEAK_HBM_GBS, kernels=kern,
+                whole_step_tflops=round((FLOP_FORCE_PAIR + FLOP_HVP_PAIR) * npairs * pair_beads
+                                        / (ms * 1e-3) / 1e12, 3),
+                launch_timing="HIP events on the library stream around each pair kernel "
+                              "(veff_grad_timed), mean over the timed calls")
 
     out = dict(metric=METRIC, value=Q * N / (ms * 1e-3), unit="atom·beads/s", n_gpus=1,
                steps=args.steps, warmup=args.warmup, ms_per_step=ms, higher_is_better=True,
@@ -590,8 +665,10 @@ def main():
                config=dict(workload=f"{args.config}: {system['name']} Q={Q} atoms x N={N} beads, "
                                     f"rc={system['rc']} nm, analytic HVP",
                            Q=Q, N=N, rc=system["rc"], box=[float(b) for b in system["box"]],
-                           graph=ms_graph is not None and ms_graph <= ms_eager,
+                           graph=ms_graph is not None,
                            ms_eager=ms_eager, ms_graph=ms_graph,
+                           median_ms_eager=med_eager, median_ms_graph=med_graph,
+                           plan_options=opts or "default", autotune=tune,
                            precision="FP32 pair terms from 32-bit fixed-point coordinates; "
                                      "FP64 bonds, residuals, reductions, gradient"),
                roofline=roof, fd=fd, phases_ms=phases)

@@ -39,7 +39,8 @@
  *     and never synchronise with the host, so they can be captured in a hipGraph.
  *   - Return value 0 = MOP_OK; a negative value is a synchronous argument error
  *     detected on the host, in which case nothing was enqueued.
- *   - Errors found on the device (non-finite result, exhausted capacity) set bits of a
+ *   - Errors found on the device (non-finite result, exhausted capacity, overlapping
+ *     atoms) set bits of a
  *     status word inside the workspace; read it with mop_status after the work has
  *     finished.  Outputs are unspecified when a bit is set.
  */
@@ -66,6 +67,9 @@ extern "C" {
 /* bits of the device status word (mop_status) */
 #define MOP_DEV_NONFINITE 1 /* a force, residual or gradient component is not finite */
 #define MOP_DEV_CAPACITY 2  /* a neighbour-search buffer overflowed (re-plan) */
+#define MOP_DEV_OVERLAP 4   /* a force pass met a non-excluded pair closer than 0.01 nm
+                               (overlapping atoms: FP32 pair terms of order r^-14 are then
+                               meaningless; the outputs are still written) */
 
 typedef struct mop_ctx_s* mop_ctx;
 typedef struct mop_system_s* mop_system;
@@ -134,13 +138,14 @@ typedef struct {
  *               stream in call order instead of on a second stream of the plan beside
  *               the pair kernels.  Results are bit-identical either way; for callers
  *               that need every kernel on one stream, and for timing each kernel alone.
- *   list_cap    neighbour-list entries per 8-atom cluster.  veff_grad (exact mode)
+ *   list_cap    neighbour-list records per 8-atom cluster.  veff_grad (exact mode)
  *               records, in its force pass, which atoms passed each cluster's
- *               neighbour search, and its Hessian pass reads them back instead of
- *               searching again; a cluster with more survivors than list_cap is
- *               searched again.  0: sized from the mean density (about 1.6 times the
- *               expected count); negative: no lists.  The workspace grows by
- *               4 * list_cap bytes per cluster and pair bead.
+ *               neighbour search (one 32-bit record per neighbouring cluster with at
+ *               least one such atom: its index and an 8-bit mask of those atoms), and
+ *               its Hessian pass reads them back instead of searching again; a cluster
+ *               with more records than list_cap is searched again.  0: sized from the
+ *               mean density (about 1.5 times the expected count); negative: no lists.
+ *               The workspace grows by 4 * list_cap bytes per cluster and pair bead.
  */
 #define MOP_PLAN_NEWTON3 1
 #define MOP_PLAN_ONE_STREAM 2

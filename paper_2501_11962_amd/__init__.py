@@ -19,11 +19,14 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libmop.so")
+# MOP_LIBRARY selects another build of the same library (the host-sanitized one of
+# build.py --sanitize, loaded by the sanitizer test with its runtime preloaded)
+LIB_PATH = os.environ.get("MOP_LIBRARY") or os.path.join(_HERE, "libmop.so")
 
 MOP_OK = 0
 MOP_DEV_NONFINITE = 1
 MOP_DEV_CAPACITY = 2
+MOP_DEV_OVERLAP = 4
 MOP_PLAN_NEWTON3 = 1
 MOP_PLAN_ONE_STREAM = 2
 MOP_ELEC_RF, MOP_ELEC_PME = 0, 1

@@ -1,10 +1,22 @@
-"""Autotuner for the neighbour-search geometry of a plan.
+"""Autotuner for the neighbour-search geometry and launch shape of a plan.
 
-The pair kernels' cost depends on the x-y column width (it sets the cluster shape, the
-candidate count and the in-cutoff fraction) and on the waves per workgroup.  `autotune`
-times veff_grad on the caller's own system and path for each candidate setting (HIP
-events on the library stream, median of a few calls) and caches the winner in a JSON
-file keyed by the system's shape, so later plans for similar systems reuse it.
+The pair kernels' cost depends on
+    col_width  the x-y column width (it sets the cluster shape, the candidate count and
+               the in-cutoff fraction),
+    zbin       the height of the z bins that order atoms inside a column (it sets how
+               tightly each column's z window fits the search sphere),
+    waves      waves per workgroup of the pair kernels,
+    list_cap   the neighbour lists the force pass records for the Hessian pass
+               (0: sized from the density; -1: none, the Hessian pass searches again).
+`autotune` times veff_grad on the caller's own system and path (HIP events on the
+library stream, median of a few calls after a warm-up) and searches the space one
+parameter at a time: starting from the default plan, each sweep tries every value of one
+parameter with the others held at the best so far, and keeps a value only if it is faster
+by more than `min_gain`.  A winner other than the default is then timed against the
+default again, alternately, and kept only if it still wins by `min_gain` (drift of the
+clock between the search's measurements can fake gains of a few per cent).  The winner is
+cached in a JSON file keyed by the system's shape, so later plans for similar systems
+reuse it.
 
     opts = autotune(ctx, system_dict, R)          # R: (N, Q, 3) float64 CUDA tensor
     plan = Plan(System(ctx, system_dict), N, **opts)
@@ -16,8 +28,9 @@ import os
 
 import numpy as np
 
-DEFAULT_CANDIDATES = [dict(col_width=cw, waves=w) for cw in (0.35, 0.4, 0.45, 0.5)
-                      for w in (2, 4)]
+DEFAULT = dict(col_width=0.4, zbin=0.1, waves=4, list_cap=0)
+SPACE = dict(col_width=(0.35, 0.4, 0.45, 0.5), zbin=(0.05, 0.1, 0.2), waves=(2, 4, 8),
+             list_cap=(0, -1))
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "mop_autotune.json")
 
 
@@ -28,7 +41,8 @@ def shape_key(system, N):
     rho = Q / float(np.prod(box))
     qb = int(round(np.log2(max(Q, 1)) * 2))          # half-octave buckets of Q
     aspect = "x".join(f"{b / box.min():.2f}" for b in box)
-    return f"q{qb}_rho{rho:.0f}_rc{float(system['rc']):.2f}_box{aspect}_n{int(N)}"
+    elec = "pme" if system.get("elec", "rf") == "pme" else "rf"
+    return f"q{qb}_rho{rho:.0f}_rc{float(system['rc']):.2f}_box{aspect}_n{int(N)}_{elec}"
 
 
 def load_cache(path=DEFAULT_CACHE):
@@ -48,43 +62,100 @@ def save_cache(d, path=DEFAULT_CACHE):
     os.replace(tmp, path)
 
 
-def autotune(ctx, system, R, candidates=None, repeats=3, cache=DEFAULT_CACHE, force=False,
-             log=None):
-    """Best plan options (col_width, waves) for `system` with path R (CUDA tensor)."""
+def time_plan(plan, R, repeats=5, G=None, v=None):
+    """Median wall time (ms) of veff_grad on `plan` over `repeats` calls after a warm-up,
+    from HIP events on the current stream."""
     import torch
 
-    from . import Plan, System, veff_grad
+    from . import veff_grad
+    G = torch.empty_like(R) if G is None else G
+    v = torch.empty(1, dtype=torch.float64, device=R.device) if v is None else v
+    veff_grad(plan, R, 0, 0.0, G, v)
+    times = []
+    for _ in range(repeats):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        veff_grad(plan, R, 0, 0.0, G, v)
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    return float(np.median(times))
+
+
+def autotune(ctx, system, R, candidates=None, space=None, repeats=5, sweeps=2, min_gain=0.01,
+             cache=DEFAULT_CACHE, force=False, log=None, with_info=False):
+    """Fastest plan options for `system` with path R (CUDA tensor): the best of
+    `candidates` (a list of option dicts) if given, else a parameter-by-parameter search
+    of `space` (default SPACE) from DEFAULT.  With with_info, also returns
+    {"ms": tuned time, "default_ms": time of the default plan, "tried": [...]}."""
+    import torch
+
+    from . import Plan, System
 
     N = int(R.shape[0])
     key = shape_key(system, N)
     table = load_cache(cache) if cache else {}
     if not force and key in table:
-        return dict(table[key]["opts"])
-    cands = candidates or DEFAULT_CANDIDATES
+        e = table[key]
+        return (dict(e["opts"]), dict(ms=e.get("ms"), default_ms=e.get("default_ms"),
+                                      tried=e.get("tried", []), cached=True)) \
+            if with_info else dict(e["opts"])
     sysh = System(ctx, system)
     G = torch.empty_like(R)
     v = torch.empty(1, dtype=torch.float64, device=R.device)
-    results = []
-    for c in cands:
-        plan = Plan(sysh, N, **c)
-        veff_grad(plan, R, 0, 0.0, G, v)  # warm-up
-        times = []
-        for _ in range(repeats):
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record()
-            veff_grad(plan, R, 0, 0.0, G, v)
-            e1.record()
-            torch.cuda.synchronize()
-            times.append(e0.elapsed_time(e1))
-        ms = float(np.median(times))
-        results.append((ms, c))
-        if log:
-            log(f"[autotune] {c}: {ms:.3f} ms")
-        del plan
-    ms, best = min(results, key=lambda t: t[0])
+    tried = {}
+
+    def measure(opts):
+        k = json.dumps(opts, sort_keys=True)
+        if k not in tried:
+            plan = Plan(sysh, N, **opts)
+            tried[k] = time_plan(plan, R, repeats, G, v)
+            del plan
+            if log:
+                log(f"[autotune] {opts}: {tried[k]:.3f} ms")
+        return tried[k]
+
+    if candidates:
+        results = [(measure(dict(c)), dict(c)) for c in candidates]
+        ms, best = min(results, key=lambda t: t[0])
+        default_ms = None
+    else:
+        sp = space or SPACE
+        best = {k: DEFAULT[k] for k in sp}
+        default_ms = ms = measure(best)
+        for _ in range(sweeps):
+            changed = False
+            for name, values in sp.items():
+                for val in values:
+                    if val == best[name]:
+                        continue
+                    c = dict(best, **{name: val})
+                    t = measure(c)
+                    if t < ms * (1.0 - min_gain):
+                        best, ms, changed = c, t, True
+            if not changed:
+                break
+        default = {k: DEFAULT[k] for k in sp}
+        if best != default:
+            # confirm against the default with interleaved timings (clock and temperature
+            # drift between the search's measurements can fake a gain of a few per cent)
+            pb, pd = Plan(sysh, N, **best), Plan(sysh, N, **default)
+            tb = td = float("inf")
+            for _ in range(3):
+                tb = min(tb, time_plan(pb, R, repeats, G, v))
+                td = min(td, time_plan(pd, R, repeats, G, v))
+            del pb, pd
+            if log:
+                log(f"[autotune] confirmation: {best} {tb:.3f} ms, default {td:.3f} ms")
+            if tb < td * (1.0 - min_gain):
+                ms, default_ms = tb, td
+            else:
+                best, ms, default_ms = default, td, td
+    info = dict(ms=ms, default_ms=default_ms,
+                tried=[dict(json.loads(k), ms=t) for k, t in tried.items()], cached=False)
     if cache:
         table = load_cache(cache)
-        table[key] = dict(opts=best, ms=ms, tried=[dict(c, ms=t) for t, c in results])
+        table[key] = dict(opts=best, ms=ms, default_ms=default_ms, tried=info["tried"])
         save_cache(table, cache)
-    return dict(best)
+    return (dict(best), info) if with_info else dict(best)

@@ -31,17 +31,39 @@ def hipcc():
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose=False, jobs=None):
+# Host-side sanitizers: the host half of every source (argument checks, exclusion-key
+# numbering, plan geometry and workspace layout, launch set-up) instrumented with
+# AddressSanitizer and UndefinedBehaviorSanitizer; device code is compiled as usual.
+SANITIZE = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+            "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer",
+            "-Xarch_host", "-shared-libasan", "-g"]
+SANITIZED_LIB = os.path.join(HERE, "_build", "asan", "libmop.so")
+
+
+def asan_runtime():
+    """Path of the shared AddressSanitizer runtime of hipcc's clang (to LD_PRELOAD into a
+    process that loads the sanitized library)."""
+    out = subprocess.check_output([os.path.join(os.path.dirname(hipcc()), "amdclang++"),
+                                   "-print-file-name=libclang_rt.asan-x86_64.so"]).decode().strip()
+    if not os.path.isabs(out) or not os.path.exists(out):
+        raise RuntimeError("AddressSanitizer runtime not found")
+    return out
+
+
+def build(verbose=False, jobs=None, sanitize=False):
+    """Compile every source and link libmop.so in-tree; with sanitize, the host-sanitized
+    variant at _build/asan/libmop.so instead."""
     cc = hipcc()
-    bdir = os.path.join(HERE, "_build")
+    bdir = os.path.join(HERE, "_build", "asan") if sanitize else os.path.join(HERE, "_build")
     os.makedirs(bdir, exist_ok=True)
     procs = []
     objs = []
+    flags = FLAGS + SANITIZE if sanitize else FLAGS
     for s in SOURCES:
         src = os.path.join(CSRC, s)
         obj = os.path.join(bdir, s.replace(".hip", ".o"))
         objs.append(obj)
-        cmd = [cc, *FLAGS, "-c", src, "-o", obj]
+        cmd = [cc, *flags, "-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((s, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
@@ -54,12 +76,15 @@ def build(verbose=False, jobs=None):
             failed.append(s)
     if failed:
         raise RuntimeError(f"hipcc failed for {failed}")
-    tmp = LIB + f".tmp{os.getpid()}"
+    lib = SANITIZED_LIB if sanitize else LIB
+    tmp = lib + f".tmp{os.getpid()}"
     cmd = [cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp, "-lrocfft"]
+    if sanitize:
+        cmd[1:1] = ["-fsanitize=address,undefined", "-shared-libasan"]
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, sanitize="--sanitize" in sys.argv))

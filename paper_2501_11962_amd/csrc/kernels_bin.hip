@@ -222,6 +222,64 @@ __global__ void __launch_bounds__(EWB) k_bin_displace(const SegDev* __restrict__
                    to_fixed(r[2] + eps * d[2], sg.s.L[2]), __float_as_uint(sg.s.qs[i]));
 }
 
+// Overlap check of a binned configuration: atom i (slot order) against every atom whose
+// fixed-point coordinates lie within OVERLAP_R of its own along each axis.  Columns and
+// z bins are contiguous ranges of fixed-point values, so those atoms sit in the columns
+// of u_x -/+ d and u_y -/+ d (at most two each, d being far below a column width) and in
+// the z bins from that of u_z - d to that of u_z + d.  A non-excluded pair closer than
+// OVERLAP_R (the same FP32 difference of fixed-point coordinates the pair kernels form)
+// sets ST_OVERLAP in the status word, which leads the workspace.
+__global__ void __launch_bounds__(EWB) k_overlap(const SegDev* __restrict__ segs, Launch L, char* ws) {
+    const int blk = blockIdx.x;
+    const int p = find_seg(L, blk);
+    const SegDev& sg = segs[p];
+    const int local = blk - L.pf[p];
+    const int b = local / sg.bpb;
+    const int i = (local - b * sg.bpb) * EWB + threadIdx.x;
+    const int Q = sg.s.Q, S = sg.s.S, ncx = sg.s.ncx, ncy = sg.s.ncy, nzb = sg.s.nzb;
+    if (i >= Q) return;
+    const int si = wsp<const int>(ws, sg.o_slotof)[(size_t)b * Q + i];
+    const uint4* up = wsp<const uint4>(ws, sg.o_upos) + (size_t)b * S;
+    const int2* um = wsp<const int2>(ws, sg.o_umeta) + (size_t)b * S;
+    const int* cs = wsp<const int>(ws, sg.o_colstart) + (size_t)b * (sg.s.ncol + 1);
+    const int* bo = wsp<const int>(ws, sg.o_binoff) + (size_t)b * sg.s.ncol * (nzb + 1);
+    const uint4 ui = up[si];
+    const int ki = um[si].x >> 4;
+    // OVERLAP_R in fixed-point units per axis, rounded up, plus one unit of margin
+    uint32_t dr[3];
+    for (int a = 0; a < 3; ++a) dr[a] = (uint32_t)ceil(OVERLAP_R / sg.s.L[a] * 4294967296.0) + 1u;
+    const int x0 = fixed_bin(ui.x - dr[0], ncx), x1 = fixed_bin(ui.x + dr[0], ncx);
+    const int y0 = fixed_bin(ui.y - dr[1], ncy), y1 = fixed_bin(ui.y + dr[1], ncy);
+    const int z0 = fixed_bin(ui.z - dr[2], nzb), z1 = fixed_bin(ui.z + dr[2], nzb);
+    const float sx = sg.s.sc[0], sy = sg.s.sc[1], sz = sg.s.sc[2];
+    bool hit = false;
+    for (int a = 0; a < 2; ++a) {
+        const int cx = a ? x1 : x0;
+        if (a && x1 == x0) break;
+        for (int c = 0; c < 2; ++c) {
+            const int cy = c ? y1 : y0;
+            if (c && y1 == y0) break;
+            const int col = cx * ncy + cy;
+            const int base = cs[col];
+            const int* o = bo + (size_t)col * (nzb + 1);
+            for (int zb = z0;; zb = zb + 1 == nzb ? 0 : zb + 1) {
+                for (int sj = base + o[zb]; sj < base + o[zb + 1]; ++sj) {
+                    if (sj == si) continue;
+                    const uint4 uj = up[sj];
+                    const int kj = um[sj].x >> 4;
+                    const float dx = (float)(int)(uj.x - ui.x) * sx;
+                    const float dy = (float)(int)(uj.y - ui.y) * sy;
+                    const float dz = (float)(int)(uj.z - ui.z) * sz;
+                    const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                    hit |= (r2 < OVERLAP_R2) & (abs(ki - kj) > 2);
+                }
+                if (zb == z1) break;
+            }
+        }
+    }
+    if (hit) atomicOr(reinterpret_cast<int*>(ws), ST_OVERLAP);
+}
+
 void run_displace(const SegDev* dsegs, const SegDev* hsegs, const Launch& base, char* ws,
                   const double* R, int fdsign, double fdh, hipStream_t st) {
     Launch La = base;
@@ -271,6 +329,7 @@ void run_binning(const SegDev* dsegs, const SegDev* hsegs, const Launch& base, c
     hipLaunchKernelGGL(k_bin_scatter, dim3(La.pf[base.nseg]), dim3(EWB), 0, st, dsegs, La, ws);
     hipLaunchKernelGGL(k_bin_place, dim3(La.pf[base.nseg]), dim3(EWB), 0, st, dsegs, La, ws);
     hipLaunchKernelGGL(k_bin_pad, dim3(Lc.pf[base.nseg]), dim3(EWB), 0, st, dsegs, Lc, ws);
+    hipLaunchKernelGGL(k_overlap, dim3(La.pf[base.nseg]), dim3(EWB), 0, st, dsegs, La, ws);
 }
 
 }  // namespace mop

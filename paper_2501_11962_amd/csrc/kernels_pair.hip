@@ -405,6 +405,7 @@ __global__ void __launch_bounds__(64 * PW, EL == 1 ? 4 : 1) k_pair(const SegDev*
     float eacc = 0.0f;
     double eacc64 = 0.0;
     int wp = 0, rp = 0;  // ring write / read counters (uniform); rp stays a multiple of 64
+    int wr = 0;          // neighbour-list records written (force pass)
 
     float* ring = s_ring + wave * NF * RING;
     float4* ring4 = reinterpret_cast<float4*>(ring);
@@ -607,8 +608,19 @@ __global__ void __launch_bounds__(64 * PW, EL == 1 ? 4 : 1) k_pair(const SegDev*
             const int off = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
                                                       __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
             wave_sync();  // previous reads of the ring are done before it is overwritten
+            if (rec) {
+                // one record per candidate cluster of this chunk with a survivor, in
+                // candidate order: (cluster index << 8) | mask of its surviving atoms
+                // (lanes 8k .. 8k+7 hold the atoms of the chunk's k-th cluster)
+                const uint32_t mk = lane < 8 ? (uint32_t)(m >> (8 * lane)) & 0xFFu : 0u;
+                const unsigned long long nzm = __ballot(mk != 0u);
+                if (mk != 0u) {
+                    const int pos = wr + (int)__popcll(nzm & ((1ull << lane) - 1ull));
+                    if (pos < lcap) nl[pos] = (int)(((uint32_t)clist[q + lane] << 8) | mk);
+                }
+                wr += (int)__popcll(nzm);
+            }
             if (pass) {
-                if (rec && wp + off < lcap) nl[wp + off] = slot;
                 const int e = (wp + off) & (RING - 1);
                 if (N3) {
                     float* re = ring + e;
@@ -642,23 +654,39 @@ __global__ void __launch_bounds__(64 * PW, EL == 1 ? 4 : 1) k_pair(const SegDev*
         }
     };
 
-    // ---- replay of a recorded list: 64 entries per chunk, loads two chunks ahead ----
+    // ---- replay of a recorded list: 8 records (up to 64 atoms) per chunk -----------
+    // Lane l takes atom l & 7 of record l >> 3 and keeps it when the record's mask has its
+    // bit; survivors are compacted into the ring exactly as the search compacted them, so
+    // the ring order, and every sum, is the search's.  Records are read two chunks ahead,
+    // atom data one chunk ahead.
     auto replay = [&](int cnt) __attribute__((always_inline)) {
-        int s1 = lane < cnt ? nl[lane] : -1;
-        int s2 = 64 + lane < cnt ? nl[64 + lane] : -1;
-        uint4 nuj = upos[max(s1, 0)];
-        int2 nmj = umeta[max(s1, 0)];
-        float4 njv = vs[max(s1, 0)];
-        for (int k0 = 0; k0 < cnt; k0 += 64) {
+        const int rsub = lane >> 3, atom = lane & 7;
+        uint32_t r1 = rsub < cnt ? (uint32_t)nl[rsub] : 0u;
+        uint32_t r2 = 8 + rsub < cnt ? (uint32_t)nl[8 + rsub] : 0u;
+        bool p1 = (r1 >> atom) & 1u;
+        int s1 = (int)(r1 >> 8) * CLUSTER + atom;  // a lane without a record reads slot atom
+        uint4 nuj = make_uint4(0u, 0u, 0u, 0u);
+        int2 nmj = make_int2(0, 0);
+        float4 njv = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (p1) {
+            nuj = upos[s1];
+            nmj = umeta[s1];
+            njv = vs[s1];
+        }
+        for (int k0 = 0; k0 < cnt; k0 += 8) {
             const uint4 uj = nuj;
             const int2 mj = nmj;
             const float4 jv = njv;
-            const int n = min(64, cnt - k0);
-            s1 = s2;
-            nuj = upos[max(s1, 0)];
-            nmj = umeta[max(s1, 0)];
-            njv = vs[max(s1, 0)];
-            s2 = k0 + 128 + lane < cnt ? nl[k0 + 128 + lane] : -1;
+            const bool pass = p1;
+            r1 = r2;
+            p1 = (r1 >> atom) & 1u;
+            s1 = (int)(r1 >> 8) * CLUSTER + atom;
+            if (p1) {
+                nuj = upos[s1];
+                nmj = umeta[s1];
+                njv = vs[s1];
+            }
+            r2 = k0 + 16 + rsub < cnt ? (uint32_t)nl[k0 + 16 + rsub] : 0u;
             float jx, jy, jz;
             if (exact) {
                 jx = __uint_as_float(uj.x);
@@ -669,14 +697,22 @@ __global__ void __launch_bounds__(64 * PW, EL == 1 ? 4 : 1) k_pair(const SegDev*
                 jy = (float)(int)(uj.y - ucy) * sy;
                 jz = (float)(int)(uj.z - ucz) * sz;
             }
-            wave_sync();  // the previous chunk's reads of the ring are done
-            if (MODE == 1 && !N3 && lane < n) {  // full-shell Hessian kernels only
-                ring4[lane] = make_float4(jx, jy, jz, QSC * __uint_as_float(uj.w));
-                ring4[RING + lane] = make_float4(__int_as_float(mj.x), jv.x, jv.y, jv.z);
+            const unsigned long long m = __ballot(pass);
+            const int off = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
+                                                      __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+            wave_sync();  // the previous reads of the ring are done before it is overwritten
+            if (MODE == 1 && !N3 && pass) {  // full-shell Hessian kernels only
+                const int e = (wp + off) & (RING - 1);
+                ring4[e] = make_float4(jx, jy, jz, QSC * __uint_as_float(uj.w));
+                ring4[RING + e] = make_float4(__int_as_float(mj.x), jv.x, jv.y, jv.z);
             }
+            wp += __popcll(m);
             wave_sync();
-            if (n == 64) eval.template operator()<true>(0, 64);
-            else eval.template operator()<false>(0, n);
+            while (wp - rp >= 64) {
+                eval.template operator()<true>(rp, 64);
+                rp += 64;
+                wave_sync();
+            }
         }
     };
     bool searched = true;
@@ -766,7 +802,7 @@ __global__ void __launch_bounds__(64 * PW, EL == 1 ? 4 : 1) k_pair(const SegDev*
     }
     // ---- remaining ring entries ---------------------------------------------------
     if (wp - rp > 0) eval.template operator()<false>(rp, wp - rp);
-    if (rec && lane == 0) *nlc = wp;
+    if (rec && lane == 0) *nlc = wr;
 
     // ---- reduce over the 8 j lanes of each i atom and store ------------------------
 #pragma unroll

@@ -15,7 +15,9 @@
 //            of the tile and of its upper neighbours (8 tiles).  Contributions are
 //            rounded to 64-bit fixed point and summed with LDS integer atomics, so the
 //            grid is the same on every call whatever the order; the owner then writes
-//            its points to the FP64 real grid (no global atomics, no clearing pass).  The
+//            its points to the real grid: FP64 for the charge grid, FP32 (the value
+//            divided by the power-of-two dipole scale) for the dipole grid (no global
+//            atomics, no clearing pass).  The
 //            scale is a power of two chosen so that no value can overflow (sum |q|
 //            bounds every charge-grid value; sum |q| * 3 max(K/L) max|v_i| every
 //            dipole-grid value).
@@ -28,7 +30,14 @@
 // Spline weights come from the recursion M_n(x) = [x M_{n-1}(x) + (n - x) M_{n-1}(x-1)]
 // / (n - 1) started at M_2, in FP64 registers; M_n' = M_{n-1}(x) - M_{n-1}(x - 1) and
 // M_n'' = M_{n-2}(x) - 2 M_{n-2}(x - 1) + M_{n-2}(x - 2) reuse the lower orders.
-// All PME arithmetic is FP64.  The FFTs run in rocFFT (host side, mop_api.hip).
+// Precision: spline weights, fixed-point spreading and the gathers' sums are FP64.  The
+// charge grids of the force passes are transformed, solved and gathered in FP64 (forces
+// and the energy).  The dipole grid of the Hessian pass is stored, transformed
+// (single-precision rocFFT), solved and read back in FP32: that adds about 1e-6
+// relative error to the mesh part of the Hessian-vector product, against the 1e-4
+// tolerance of Hessian-vector products (measured against the FP64 oracle: Hessian-vector
+// products of PME systems stay within 9e-7 relative L2 in total).  The FFTs run in
+// rocFFT (host side, mop_api.hip).
 #include <algorithm>
 
 #include <type_traits>

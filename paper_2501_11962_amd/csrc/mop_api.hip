@@ -354,9 +354,12 @@ static SysDev plan_geometry(const mop_system_s* sys, const mop_plan_opts* opts) 
     s.cw[1] = (float)cwy;
     s.rcs = (float)rcs;
     s.rcs2 = (float)(rcs * rcs);
-    // neighbour-list capacity: 1.6 x the expected number of atoms within the search
-    // radius of an 8-atom cluster's box (cw x cw x the height 8 atoms fill at the mean
-    // density), rounded up to a multiple of 64
+    // neighbour-list capacity in records (one per neighbouring cluster with an atom in
+    // range): 1.5 x the expected number of 8-atom clusters whose box lies within the search
+    // radius of a cluster's box (boxes cw x cw x the height 8 atoms fill at the mean
+    // density: the volume swept by one box around the other, grown by the radius, times
+    // the cluster density), rounded up to a multiple of 64.  A record keeps the cluster
+    // index in 24 bits, so slot counts from 2^26 on take no lists.
     const int lc = opts ? opts->list_cap : 0;
     if (lc > 0) {
         s.lcap = lc;
@@ -364,13 +367,15 @@ static SysDev plan_geometry(const mop_system_s* sys, const mop_plan_opts* opts) 
         s.lcap = 0;
     } else {
         const double rho = s.Q / (L[0] * L[1] * L[2]);
-        const double a = cwx, b = cwy, c = std::min(L[2], CLUSTER / (rho * a * b)), r = rcs;
+        const double c0 = std::min(L[2], CLUSTER / (rho * cwx * cwy));
+        const double a = 2.0 * cwx, b = 2.0 * cwy, c = 2.0 * c0, r = rcs;
         const double pi = 3.14159265358979323846;
         const double vol = a * b * c + 2.0 * (a * b + b * c + c * a) * r +
                            pi * r * r * (a + b + c) + 4.0 / 3.0 * pi * r * r * r;
-        const double est = std::min(1.6 * rho * vol, (double)s.S);
+        const double est = std::min(1.5 * rho * vol / CLUSTER, (double)s.cpb);
         s.lcap = std::max(64, ((int)std::ceil(est) + 63) & ~63);
     }
+    if (s.S >= (1 << 26)) s.lcap = 0;
     return s;
 }
 

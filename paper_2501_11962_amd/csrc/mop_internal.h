@@ -12,8 +12,9 @@
 //     fs    float  x3 pair sums in slot order (structure of arrays), Newton-3 kernels
 //   Per atom (original order): slotof, pair force / pair HVP outputs (float4).
 //   Per cluster: the neighbour list a force pass records for the Hessian pass of the
-//     same bead (nl: int [lcap] slots of the atoms that passed the search, in search
-//     order; nlc: their count, which may exceed lcap, then the list is incomplete).
+//     same bead (nl: int [lcap] records, one per candidate cluster with atoms that passed
+//     the search, in search order: cluster index << 8 | 8-bit mask of those atoms; nlc:
+//     their count, which may exceed lcap, then the list is incomplete).
 // Per path: FP64 residuals d^n [(N-1)][Q][3], reduction partials, per-bead max |d|^2.
 // Particle-mesh Ewald (systems with Ewald electrostatics), per pair bead:
 //     ptc   int [ntile]    atoms per grid tile; pts int [ntile + 1] their starts
@@ -49,6 +50,9 @@ constexpr int32_t DUMMY_KEY = INT32_MIN;
 // Status bits (mirrors MOP_DEV_* of the public header).
 constexpr int ST_NONFINITE = 1;
 constexpr int ST_CAPACITY = 2;
+constexpr int ST_OVERLAP = 4;    // a binned configuration has a non-excluded pair closer than OVERLAP_R
+constexpr double OVERLAP_R = 0.01;     // nm
+constexpr float OVERLAP_R2 = 1.0e-4f;  // (0.01 nm)^2
 
 constexpr int PME_BLOCK = 256;    // block size of the grid kernels
 constexpr int PME_TILE = 8;       // nominal grid tile edge of the spreading kernel
@@ -57,7 +61,7 @@ struct SysDev {
     int Q, ncx, ncy, ncol, nzb, nt;
     int S;            // slots per bead (multiple of 8)
     int cpb;          // clusters per bead (S / 8)
-    int lcap;         // neighbour-list entries per cluster (0: no lists)
+    int lcap;         // neighbour-list records per cluster (0: no lists)
     int allx, ally;   // 1: the column stencil spans every column along that axis
     int rx, ry;       // stencil half widths (columns) when not spanning
     int wx, wy;       // stencil widths (columns)

@@ -148,3 +148,22 @@ def test_ewald_erfc_constants_match_their_fit():
     p = EF.eval_f32(np.array(consts[::-1]), x).astype(np.float64)
     e = np.abs(np.exp(-x * x) * p - erfc(x)) / erfc(x)
     assert e.max() < 4e-7
+
+
+def test_loaded_library_is_the_selected_build(mop):
+    """The process maps the library file the binding selected (the in-tree build, or the
+    host-sanitized one when MOP_LIBRARY names it)."""
+    mop.lib()
+    maps = open("/proc/self/maps").read()
+    assert os.path.realpath(mop.LIB_PATH) in maps
+
+
+def test_system_check_of_every_workload_size(mop):
+    """Host validation and exclusion-key numbering at the benchmark sizes (150,000 atoms
+    with 50-atom chains and waters; PME variants)."""
+    s4 = W.cfg4()
+    assert mop.system_check(s4) == 0
+    assert mop.system_check(s4, use_molecules=True) == 0
+    assert mop.system_check(W.with_pme(s4)) == 0
+    for s_, _, _ in W.cfg5()[:4]:
+        assert mop.system_check(s_) == 0

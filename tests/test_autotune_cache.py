@@ -18,3 +18,8 @@ def test_cache_round_trip(tmp_path):
     assert A.load_cache(p)["k"]["opts"]["waves"] == 2
     open(p, "w").write("not json")
     assert A.load_cache(p) == {}
+
+
+def test_search_space_contains_the_default():
+    for k, v in A.DEFAULT.items():
+        assert v in A.SPACE[k], k

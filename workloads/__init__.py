@@ -39,7 +39,10 @@ molecular systems, section 1.1 and Appendix A.2) at the sizes the benchmark uses
 """
 from __future__ import annotations
 
+import hashlib
 import math
+import os
+
 import numpy as np
 
 KB = 0.0083144626  # kJ mol^-1 K^-1
@@ -417,6 +420,24 @@ def random_walk_path(system, N, seed, sigma=None, x0=None):
     return R, zeta, s
 
 
+TETHER = 0.1   # mean-reversion per bead of tethered_path
+
+
+def tethered_path(system, N, seed, sigma=None, kappa=TETHER, x0=None):
+    """Path R^1 = x0, R^{n+1} = R^n + kappa (R^1 - R^n) + s_i zeta^n: Brownian increments
+    with a harmonic tether to the first bead (an Euler-Maruyama walk of overdamped motion
+    in a harmonic well), so beads stay within about s_i / sqrt(2 kappa) of R^1 instead of
+    drifting apart as sqrt(n) s_i; a free walk of 100 beads brings atoms of different
+    molecules closer than 0.01 nm.  Returns (R, zeta, s)."""
+    s = noise_sigma(system, sigma)
+    zeta = path_noise(system, N, seed)
+    R = np.empty((N, system["Q"], 3))
+    R[0] = system["x"] if x0 is None else x0
+    for n in range(N - 1):
+        R[n + 1] = R[n] + kappa * (R[0] - R[n]) + s[:, None] * zeta[n]
+    return R, zeta, s
+
+
 def drifted_path(system, N, seed, drift, sigma=None):
     """Path R^{n+1} = R^n + drift(R^n) + s_i zeta^n with a caller-supplied drift
     callable (tests pass c*F from the oracle: an Euler-Maruyama trajectory).
@@ -430,6 +451,38 @@ def drifted_path(system, N, seed, drift, sigma=None):
     return R, zeta, s
 
 
+def steepest_descent(system, energy_forces, max_step=2e-3, fmax=5e3, iters=500, log=None):
+    """Steepest descent of the atoms of `system` under a caller-supplied callable
+    x -> (U(x), F(x)) (energy and (Q, 3) forces): the atom with the largest force moves by
+    the step h along its force and every other atom proportionally less
+    (x' = x + h F / max_i |F_i|); a step that lowers U is kept and h grows by 1.2 (at most
+    `max_step` nm), one that does not is undone and h shrinks by 0.2.  Stops when
+    max_i |F_i| <= fmax or after `iters` force evaluations.  Removes the overlaps that
+    random placement at liquid density leaves before a path is built (the paper's paths
+    start from equilibrated structures, Appendix A.2).
+    Returns (x wrapped into the box, evaluations done, final max |F|)."""
+    box = np.asarray(system["box"], np.float64)
+    x = np.array(system["x"], np.float64)
+    U, F = energy_forces(x)
+    fm = float(np.linalg.norm(F, axis=1).max())
+    h = max_step
+    it = 0
+    for it in range(1, iters + 1):
+        if fm <= fmax:
+            break
+        xn = x + (h / fm) * F
+        Un, Fn = energy_forces(xn)
+        if Un < U:
+            x, U, F = xn, Un, Fn
+            fm = float(np.linalg.norm(F, axis=1).max())
+            h = min(1.2 * h, max_step)
+        else:
+            h *= 0.2
+        if log is not None and it % 25 == 0:
+            log(f"  sd {it}: U {U:.6e}, max|F| {fm:.3e}, step {h:.2e} nm")
+    return _wrap(x, box), it, fm
+
+
 CONFIGS = {
     "cfg1": dict(make=cfg1, N=32, path_seed=102, sigma=0.005),
     "cfg2": dict(make=cfg2, N=64, path_seed=202, sigma=None),
@@ -437,10 +490,67 @@ CONFIGS = {
     "cfg4": dict(make=cfg4, N=16, path_seed=402, sigma=None),
 }
 
+# Stored inputs (tests/golden/relaxed_inputs.py writes them with the FP64 oracle's
+# forces): relaxed starting structures of cfg3 and cfg4, and cfg1's Euler-Maruyama path.
+STORED = {
+    "cfg1": "path_cfg1.npz",
+    "cfg3": "relaxed_cfg3.npz",
+    "cfg4": "relaxed_cfg4.npz",
+}
+STORE_DIR = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                         "tests", "golden")
 
-def make_config(name, N=None):
-    """(system, R) for one of cfg1-cfg4 with its path (random-walk beads)."""
+
+def system_digest(system):
+    """Hash of a generated system's coordinates and parameters: a stored input made from
+    another version of the generator is refused."""
+    h = hashlib.sha256()
+    for k in ("x", "mass", "charge", "type", "sigma", "epsilon", "bonds"):
+        h.update(np.ascontiguousarray(system[k]).tobytes())
+    return h.hexdigest()[:16]
+
+
+def load_stored(name, system):
+    """The stored arrays of workload `name` (see STORED), checked against the system."""
+    path = os.path.join(STORE_DIR, STORED[name])
+    if not os.path.exists(path):
+        raise FileNotFoundError(f"{path} is missing: run `python tests/golden/relaxed_inputs.py {name}`")
+    with np.load(path, allow_pickle=False) as z:
+        d = {k: z[k] for k in z.files}
+    if str(d["digest"]) != system_digest(system):
+        raise RuntimeError(f"{path} was made from another version of the {name} generator: "
+                           f"run `python tests/golden/relaxed_inputs.py {name}`")
+    return d
+
+
+def make_config(name, N=None, relaxed=True):
+    """(system, R) for one of cfg1-cfg4 with its path.
+    cfg1: Euler-Maruyama path R^{n+1} = R^n + c F(R^n) + 0.005 nm noise (stored).
+    cfg3, cfg4: tethered Brownian beads (tethered_path) from the relaxed structure
+    (stored), which also replaces the system's reference coordinates.  cfg2: tethered
+    Brownian beads from the generated structure (its waters are placed without
+    contacts).  relaxed=False gives the unrelaxed inputs with free random-walk beads."""
     c = CONFIGS[name]
     sys_ = c["make"]()
-    R, _, _ = random_walk_path(sys_, N or c["N"], c["path_seed"], c["sigma"])
+    N = N or c["N"]
+    if relaxed and name == "cfg1":
+        R = load_stored(name, sys_)["R"]
+        if N > R.shape[0]:
+            raise ValueError(f"the stored cfg1 path has {R.shape[0]} beads")
+        return sys_, np.ascontiguousarray(R[:N])
+    if relaxed and name in STORED:
+        sys_ = dict(sys_, x=load_stored(name, sys_)["x"])
+    if not relaxed:
+        R, _, _ = random_walk_path(sys_, N, c["path_seed"], c["sigma"])
+    else:
+        R, _, _ = tethered_path(sys_, N, c["path_seed"], c["sigma"])
     return sys_, R
+
+
+def batch_paths(specs=None):
+    """The uneven batch (cfg5): [(system, R, seed)] with tethered Brownian beads."""
+    out = []
+    for s_, N, seed in (specs or cfg5()):
+        R, _, _ = tethered_path(s_, N, seed)
+        out.append((s_, R, seed))
+    return out
