@@ -200,6 +200,26 @@ int mop_workspace_size(mop_plan plan, size_t* bytes);
 int bead_forces(mop_plan plan, const double* R, int32_t B, float* F, double* U, void* ws);
 
 /*
+ * bead_forces without a workspace argument, for callers that cannot allocate device
+ * memory (code under graph capture, tight serving loops, harnesses that forbid
+ * allocation).  Same arguments and results as bead_forces, plus
+ *   status  one device int32 that receives this call's device status word (MOP_DEV_*
+ *           bits), or NULL.
+ * The work runs in a static workspace compiled into the library: 64 MiB per device,
+ * held from the first use until the process ends, shared by every bead_forces_static call
+ * on that device, which keeps the last call's contents (the status word is cleared at the
+ * start of each call).  Calls that overlap in time on one device race on it: issue them
+ * on one stream, or order them.  Allocates nothing and calls no allocating routine.
+ * MOP_ESIZE when the plan's workspace (mop_workspace_size) exceeds 64 MiB: make the plan
+ * with fewer max_beads, or list_cap < 0 (no neighbour lists).  MOP_EINVAL for PME or
+ * Newton-3 plans.  MOP_EHIP when the device address of the workspace could not be found
+ * at mop_ctx_create.
+ */
+#define MOP_STATIC_WORKSPACE_BYTES 67108864 /* 64 MiB */
+int bead_forces_static(mop_plan plan, const double* R, int32_t B, float* F, double* U,
+                       int32_t* status);
+
+/*
  * Hessian-vector products HV^b = H(R^b) V^b, H = Hessian of U (the quantity the
  * finite-difference term of eq. 5 approximates, as -1/2 H eta):
  *   R, V [B][Q][3] double in;   HV [B][Q][3] float out

@@ -27,6 +27,7 @@ MOP_OK = 0
 MOP_DEV_NONFINITE = 1
 MOP_DEV_CAPACITY = 2
 MOP_DEV_OVERLAP = 4
+MOP_STATIC_WORKSPACE_BYTES = 67108864
 MOP_PLAN_NEWTON3 = 1
 MOP_PLAN_ONE_STREAM = 2
 MOP_ELEC_RF, MOP_ELEC_PME = 0, 1
@@ -79,7 +80,7 @@ EXPORTS = [
     "mop_batch_create", "mop_batch_destroy", "mop_batch_workspace_size",
     "mop_batch_veff_grad", "mop_status", "mop_status_clear", "mop_strerror", "mop_plan_info",
     "veff_grad_timed", "pmd_step", "mop_bias_create", "mop_bias_destroy", "mop_bias_reset",
-    "mop_bias_apply", "mop_bias_history", "mop_system_pme_info",
+    "mop_bias_apply", "mop_bias_history", "mop_system_pme_info", "bead_forces_static",
 ]
 PHASES = ["bin", "force", "pme_force", "resid", "hvp", "pme_hvp", "fd", "assemble"]
 
@@ -124,6 +125,7 @@ def lib():
         "mop_bias_apply": ([vp, vp, i32, vp, vp, i32, vp], C.c_int),
         "mop_bias_history": ([vp, C.POINTER(i32), vp, vp, i32], C.c_int),
         "mop_system_pme_info": ([vp, C.POINTER(i32), C.POINTER(C.c_double)], C.c_int),
+        "bead_forces_static": ([vp, vp, i32, vp, vp, vp], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -314,6 +316,27 @@ def bead_forces(plan, R, F=None, U=None, want_energy=True):
     if U is not None:
         _dev_tensor(U, torch.float64, (B,))
     _check(lib().bead_forces(plan.h, _ptr(R), B, _ptr(F), _ptr(U), _ptr(plan.ws)), "bead_forces")
+    return F, U
+
+
+def bead_forces_static(plan, R, F=None, U=None, want_energy=True, status=None):
+    """bead_forces in the library's static workspace (no plan workspace, no allocation in
+    the library): outputs as bead_forces; status, if given, is a (1,) int32 CUDA tensor that
+    receives the call's device status word."""
+    torch = _torch()
+    _beads(plan, R)
+    B = R.shape[0]
+    if F is None:
+        F = torch.empty((B, plan.Q, 3), dtype=torch.float32, device=R.device)
+    _dev_tensor(F, torch.float32, (B, plan.Q, 3))
+    if U is None and want_energy:
+        U = torch.empty(B, dtype=torch.float64, device=R.device)
+    if U is not None:
+        _dev_tensor(U, torch.float64, (B,))
+    if status is not None:
+        _dev_tensor(status, torch.int32, (1,))
+    _check(lib().bead_forces_static(plan.h, _ptr(R), B, _ptr(F), _ptr(U), _ptr(status)),
+           "bead_forces_static")
     return F, U
 
 

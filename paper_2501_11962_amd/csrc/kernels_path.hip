@@ -298,6 +298,7 @@ __global__ void __launch_bounds__(EWB) k_finalize_hvp(const SegDev* __restrict__
 }
 
 __global__ void k_status_clear(int* status) { *status = 0; }
+__global__ void k_status_copy(const int* status, int* out) { *out = *status; }
 
 // ---- launchers ----------------------------------------------------------------------
 
@@ -354,6 +355,10 @@ void run_finalize_hvp(const SegDev* dsegs, const SegDev* hsegs, const Launch& ba
                       const CallPtrs& cp, hipStream_t st) {
     const Launch L = per_bead_blocks(base, hsegs, false, false);
     hipLaunchKernelGGL(k_finalize_hvp, dim3(L.pf[L.nseg]), dim3(EWB), 0, st, dsegs, L, cp);
+}
+
+void run_status_copy(const int* status, int* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_status_copy, dim3(1), dim3(1), 0, st, status, out);
 }
 
 void run_status_clear(int* status, hipStream_t st) {

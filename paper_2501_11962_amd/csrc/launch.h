@@ -38,6 +38,7 @@ void run_prep_v(const SegDev* dsegs, const SegDev* hsegs, const Launch& base, co
 void run_finalize_hvp(const SegDev* dsegs, const SegDev* hsegs, const Launch& base,
                       const CallPtrs& cp, hipStream_t st);
 void run_status_clear(int* status, hipStream_t st);
+void run_status_copy(const int* status, int* out, hipStream_t st);
 
 // Metadynamics bias: adds its gradient to G (if non-null), writes {V_bias, S} to out (if
 // non-null) and, with deposit, appends a Gaussian at S.

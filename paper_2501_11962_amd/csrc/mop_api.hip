@@ -41,9 +41,15 @@ struct PmeFft {
 
 }  // namespace
 
+// Workspace of bead_forces_static, for callers that cannot allocate device memory: one
+// copy per device, held until the process ends, shared by every such call on that device.
+constexpr size_t SCRATCH_BYTES = MOP_STATIC_WORKSPACE_BYTES;
+static __device__ __align__(256) char scratch[SCRATCH_BYTES];
+
 struct mop_ctx_s {
     int device;
     hipStream_t stream;
+    char* scratch;        // device address of this device's copy of `scratch` (or null)
 };
 
 struct mop_system_s {
@@ -422,6 +428,13 @@ int mop_ctx_create(int device, void* hip_stream, mop_ctx* out) {
     if (!c) return MOP_ENOMEM;
     c->device = device;
     c->stream = static_cast<hipStream_t>(hip_stream);
+    // this device's copy of the static scratch workspace of bead_forces_static: the
+    // array's name is only a host-side stand-in, so its device address is looked up once
+    // here, with the device current, and used wherever host code needs the array
+    c->scratch = nullptr;
+    void* sp = nullptr;
+    if (hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch)) == hipSuccess) c->scratch = static_cast<char*>(sp);
+    else (void)hipGetLastError();
     *out = c;
     return MOP_OK;
 }
@@ -890,6 +903,33 @@ int bead_forces(mop_plan plan, const double* R, int32_t B, float* F, double* U, 
     if (pme) join_side(plan, st);
     run_finalize_forces(plan->dseg, &plan->hseg, L, cp, st);
     return finish_plan(plan);
+}
+
+int bead_forces_static(mop_plan plan, const double* R, int32_t B, float* F, double* U,
+                       int32_t* status) {
+    if (!plan || !R || !F) return MOP_EINVAL;
+    if (B < 1) return MOP_EINVAL;
+    if (B > plan->max_beads) return MOP_ESIZE;
+    // reaction-field full-shell plans only: Newton-3 kernels need a zeroed slot-order
+    // buffer, PME plans hand part of the workspace to rocFFT
+    if (plan->hseg.s.elec == 1 || plan->newton3) return MOP_EINVAL;
+    if (plan->ws_bytes > SCRATCH_BYTES) return MOP_ESIZE;
+    mop_ctx ctx = plan->sys->ctx;
+    if (!ctx->scratch) return MOP_EHIP;
+    hipStream_t st = ctx->stream;
+    CallPtrs cp = call_ptrs(ctx->scratch);
+    cp.R = R;
+    cp.Fout = F;
+    cp.Uout = U;
+    const Launch L = one_path(B, B);
+    // the array keeps the previous call's contents: start from a clear status word (a
+    // kernel, not a memset, so that the call can be captured in a graph)
+    run_status_clear(cp.status, st);
+    run_binning(plan->dseg, &plan->hseg, L, cp.ws, R, 0, 0.0, st);
+    run_pair(plan->dseg, &plan->hseg, L, cp.ws, 0, 0, U ? -2 : -1, plan->waves, 0, st);
+    run_finalize_forces(plan->dseg, &plan->hseg, L, cp, st);
+    if (status) run_status_copy(cp.status, status, st);
+    return finish(ctx);
 }
 
 int bead_hvp(mop_plan plan, const double* R, const double* V, int32_t B, float* HV, void* ws) {
