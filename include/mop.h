@@ -239,9 +239,10 @@ int veff_energy(mop_plan plan, const double* R, int32_t N, double* veff, double*
  * finite-difference term of eq. (5), [F(R + eps d) - F(R - eps d)]/(4 eps), with
  * eps = fd_h / max_i |d^n_i| per bead (fd_h in nm, > 0), each displaced configuration
  * re-binned.  mode 2: the same finite differences with the binning of R kept for the
- * displaced configurations (only the coordinates are rewritten); exact for fd_h up to
- * the neighbour search margin (1e-4 nm); beyond it, pairs that cross the cut-off during
- * the displacement may be missed.  G = -F_eff of eqs. (5)-(7).
+ * displaced configurations (only the coordinates are rewritten) and the neighbour lists of
+ * R's force pass replayed; exact for fd_h up to half the neighbour-search margin (1e-4
+ * nm); beyond it, pairs that cross the cut-off during the displacement may be missed.
+ * G = -F_eff of eqs. (5)-(7).
  */
 int veff_grad(mop_plan plan, const double* R, int32_t N, double* G, double* veff,
               int32_t mode, double fd_h, void* ws);
@@ -352,7 +353,7 @@ int mop_status_clear(mop_plan plan, void* ws);
  * host, so it must not be captured in a graph.
  */
 #define MOP_NPHASES 8
-#define MOP_PHASE_BIN 0       /* fixed point, histogram, scans, scatter, padding */
+#define MOP_PHASE_BIN 0       /* fixed point, histogram, scans, scatter, padding, overlap check */
 #define MOP_PHASE_FORCE 1     /* pair-force kernel, beads 1..N-1 (energy of bead 1) */
 #define MOP_PHASE_PME_FORCE 2 /* PME mesh forces beyond the pair kernel they run beside */
 #define MOP_PHASE_RESID 3     /* residuals, spring energy, FP32 copy of d */

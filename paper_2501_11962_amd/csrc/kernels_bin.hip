@@ -222,7 +222,7 @@ __global__ void __launch_bounds__(EWB) k_bin_displace(const SegDev* __restrict__
                    to_fixed(r[2] + eps * d[2], sg.s.L[2]), __float_as_uint(sg.s.qs[i]));
 }
 
-// Overlap check of a binned configuration: atom i (slot order) against every atom whose
+// Overlap check of a binned configuration: the atom of each slot against every atom whose
 // fixed-point coordinates lie within OVERLAP_R of its own along each axis.  Columns and
 // z bins are contiguous ranges of fixed-point values, so those atoms sit in the columns
 // of u_x -/+ d and u_y -/+ d (at most two each, d being far below a column width) and in
@@ -234,17 +234,20 @@ __global__ void __launch_bounds__(EWB) k_overlap(const SegDev* __restrict__ segs
     const int p = find_seg(L, blk);
     const SegDev& sg = segs[p];
     const int local = blk - L.pf[p];
-    const int b = local / sg.bpb;
-    const int i = (local - b * sg.bpb) * EWB + threadIdx.x;
-    const int Q = sg.s.Q, S = sg.s.S, ncx = sg.s.ncx, ncy = sg.s.ncy, nzb = sg.s.nzb;
-    if (i >= Q) return;
-    const int si = wsp<const int>(ws, sg.o_slotof)[(size_t)b * Q + i];
+    const int S = sg.s.S, ncx = sg.s.ncx, ncy = sg.s.ncy, nzb = sg.s.nzb;
+    const int bps = (S + EWB - 1) / EWB;  // blocks per bead (slot order)
+    const int b = local / bps;
+    const int si = (local - b * bps) * EWB + threadIdx.x;
+    if (si >= S) return;
     const uint4* up = wsp<const uint4>(ws, sg.o_upos) + (size_t)b * S;
     const int2* um = wsp<const int2>(ws, sg.o_umeta) + (size_t)b * S;
     const int* cs = wsp<const int>(ws, sg.o_colstart) + (size_t)b * (sg.s.ncol + 1);
     const int* bo = wsp<const int>(ws, sg.o_binoff) + (size_t)b * sg.s.ncol * (nzb + 1);
+    const int2 mi = um[si];
+    // slots past the last column and padding slots hold no atom
+    if (si >= cs[sg.s.ncol] || mi.x == DUMMY_KEY) return;
     const uint4 ui = up[si];
-    const int ki = um[si].x >> 4;
+    const int ki = mi.x >> 4;
     // OVERLAP_R in fixed-point units per axis, rounded up, plus one unit of margin
     uint32_t dr[3];
     for (int a = 0; a < 3; ++a) dr[a] = (uint32_t)ceil(OVERLAP_R / sg.s.L[a] * 4294967296.0) + 1u;
@@ -329,7 +332,11 @@ void run_binning(const SegDev* dsegs, const SegDev* hsegs, const Launch& base, c
     hipLaunchKernelGGL(k_bin_scatter, dim3(La.pf[base.nseg]), dim3(EWB), 0, st, dsegs, La, ws);
     hipLaunchKernelGGL(k_bin_place, dim3(La.pf[base.nseg]), dim3(EWB), 0, st, dsegs, La, ws);
     hipLaunchKernelGGL(k_bin_pad, dim3(Lc.pf[base.nseg]), dim3(EWB), 0, st, dsegs, Lc, ws);
-    hipLaunchKernelGGL(k_overlap, dim3(La.pf[base.nseg]), dim3(EWB), 0, st, dsegs, La, ws);
+    Launch Ls = base;  // overlap check: one thread per slot
+    Ls.pf[0] = 0;
+    for (int p = 0; p < base.nseg; ++p)
+        Ls.pf[p + 1] = Ls.pf[p] + base.nb[p] * ((hsegs[p].s.S + EWB - 1) / EWB);
+    hipLaunchKernelGGL(k_overlap, dim3(Ls.pf[base.nseg]), dim3(EWB), 0, st, dsegs, Ls, ws);
 }
 
 }  // namespace mop

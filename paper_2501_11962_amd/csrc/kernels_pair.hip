@@ -12,15 +12,15 @@
 //      centre (exact integer minimum image, then one rounding) and kept when within the
 //      cutoff of the i-cluster's bounding box.  Survivors are compacted (ballot + mbcnt)
 //      into a per-wave LDS ring.
-//   3. Every 64 ring entries, 8 steps of 8 j-atoms x 8 i-atoms (lane = 8*i + j) evaluate
-//      the pair terms; each lane accumulates a partial sum for its i atom.
+//   3. Every EB (64) ring entries, EB/8 steps of 8 j-atoms x 8 i-atoms (lane = 8*i + j)
+//      evaluate the pair terms; each lane accumulates a partial sum for its i atom.
 //   4. Partial sums are reduced over the 8 j lanes.
 //
 // Two variants:
 //   N3 = 1 (opt-in): Newton's third law.  A wave takes only clusters with a larger
 //      index than its own, so every pair of distinct clusters is evaluated once.  The
 //      j-side contribution of a step is added to the ring entry with an LDS atomic and,
-//      once per 64 entries, flushed to a slot-order FP32 buffer with one global atomic
+//      once per EB entries, flushed to a slot-order FP32 buffer with one global atomic
 //      per entry; i-sums are added the same way.  The own cluster is one 8 x 8 block
 //      evaluated from both sides.  Summation order depends on scheduling.
 //   N3 = 0 (default): every pair evaluated from both sides; no atomics; run-to-run
@@ -53,6 +53,16 @@
 #include "launch.h"
 
 namespace mop {
+
+// Ring entries evaluated per batch (EB / 8 steps of 8 j-atoms), as soon as that many wait.
+// Each lane sums its entries in ring order, so the batch size changes no result; measured
+// on the membrane workload, batches of 32 and 16 were 2% and 8% slower than 64 (the fixed
+// cost of a batch outweighs the better spread of pair work between candidate loads).
+#ifndef MOP_EVAL_BATCH
+#define MOP_EVAL_BATCH 64
+#endif
+constexpr int EB = MOP_EVAL_BATCH;
+static_assert(EB % 8 == 0 && EB <= 64 && RING % EB == 0, "evaluation batch");
 
 // Ring of j-atoms, one per wave in LDS (ints stored as float bits; the key word is the
 // packed 16 * exclusion key + LJ type of the system's key table).  Full-shell kernels keep
@@ -404,7 +414,7 @@ __global__ void __launch_bounds__(64 * PW, EL == 1 ? 4 : 1) k_pair(const SegDev*
     float ax = 0.f, ay = 0.f, az = 0.f;
     float eacc = 0.0f;
     double eacc64 = 0.0;
-    int wp = 0, rp = 0;  // ring write / read counters (uniform); rp stays a multiple of 64
+    int wp = 0, rp = 0;  // ring write / read counters (uniform); rp stays a multiple of EB
     int wr = 0;          // neighbour-list records written (force pass)
 
     float* ring = s_ring + wave * NF * RING;
@@ -415,7 +425,7 @@ __global__ void __launch_bounds__(64 * PW, EL == 1 ? 4 : 1) k_pair(const SegDev*
     // the search, the Hessian pass of the same bead replays them
     const int lcap = sg->s.lcap;
     const bool rec = !N3 && MODE == 0 && lists == 1 && lcap > 0;
-    const bool rpl = !N3 && MODE == 1 && lists == 2 && lcap > 0;
+    const bool rpl = !N3 && lists == 2 && lcap > 0;
     int* __restrict__ nl = nullptr;
     int* __restrict__ nlc = nullptr;
     if (rec || rpl) {
@@ -466,13 +476,13 @@ __global__ void __launch_bounds__(64 * PW, EL == 1 ? 4 : 1) k_pair(const SegDev*
     }
 
     // ---- 8 j-atoms x 8 i-atoms per step from ring entries [base, base + count) ------
-    // base is a multiple of 64, so reads of a chunk never wrap and every field of every
+    // base is a multiple of EB, so reads of a chunk never wrap and every field of every
     // step is one immediate offset from the same address.
     auto eval_t = [&]<bool EX, bool WE, bool FULL>(int base, int count)
                       __attribute__((always_inline)) {
         float* rb = ring + (base & (RING - 1)) + jslot;
         const int e0 = (base & (RING - 1)) + jslot;
-        const int nsteps = FULL ? 8 : (count + 7) >> 3;
+        const int nsteps = FULL ? EB / 8 : (count + 7) >> 3;
 #pragma unroll
         for (int s = 0; s < nsteps; ++s) {
             const int o = s * 8;
@@ -544,7 +554,7 @@ __global__ void __launch_bounds__(64 * PW, EL == 1 ? 4 : 1) k_pair(const SegDev*
             // j-side sums of this chunk (stored with the sign of the i side) go to the
             // slot-order buffer, one entry per lane
             wave_sync();
-            if (FULL || lane < count) {
+            if (FULL ? lane < EB : lane < count) {
                 const int e = (base & (RING - 1)) + lane;
                 const int slot = __float_as_int(ring[F_S * RING + e]);
                 unsafeAtomicAdd(fsx + slot, -ring[(F_J + 0) * RING + e]);
@@ -610,13 +620,15 @@ __global__ void __launch_bounds__(64 * PW, EL == 1 ? 4 : 1) k_pair(const SegDev*
             wave_sync();  // previous reads of the ring are done before it is overwritten
             if (rec) {
                 // one record per candidate cluster of this chunk with a survivor, in
-                // candidate order: (cluster index << 8) | mask of its surviving atoms
-                // (lanes 8k .. 8k+7 hold the atoms of the chunk's k-th cluster)
-                const uint32_t mk = lane < 8 ? (uint32_t)(m >> (8 * lane)) & 0xFFu : 0u;
+                // candidate order: (cluster index << 8) | mask of its surviving atoms.
+                // Lanes 8k .. 8k+7 hold the atoms of the chunk's k-th cluster; lane 8k
+                // writes its record (its slot is the cluster's first).
+                const uint32_t mk = (lane & 7) == 0 ? (uint32_t)(m >> lane) & 0xFFu : 0u;
                 const unsigned long long nzm = __ballot(mk != 0u);
                 if (mk != 0u) {
-                    const int pos = wr + (int)__popcll(nzm & ((1ull << lane) - 1ull));
-                    if (pos < lcap) nl[pos] = (int)(((uint32_t)clist[q + lane] << 8) | mk);
+                    const int pos = wr + __builtin_amdgcn_mbcnt_hi(
+                        (unsigned)(nzm >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)nzm, 0u));
+                    if (pos < lcap) nl[pos] = (int)(((uint32_t)slot << 5) | mk);
                 }
                 wr += (int)__popcll(nzm);
             }
@@ -646,9 +658,9 @@ __global__ void __launch_bounds__(64 * PW, EL == 1 ? 4 : 1) k_pair(const SegDev*
             }
             wp += __popcll(m);
             wave_sync();
-            while (wp - rp >= 64) {
-                eval.template operator()<true>(rp, 64);
-                rp += 64;
+            while (wp - rp >= EB) {
+                eval.template operator()<true>(rp, EB);
+                rp += EB;
                 wave_sync();
             }
         }
@@ -671,7 +683,7 @@ __global__ void __launch_bounds__(64 * PW, EL == 1 ? 4 : 1) k_pair(const SegDev*
         if (p1) {
             nuj = upos[s1];
             nmj = umeta[s1];
-            njv = vs[s1];
+            if (MODE == 1) njv = vs[s1];
         }
         for (int k0 = 0; k0 < cnt; k0 += 8) {
             const uint4 uj = nuj;
@@ -684,7 +696,7 @@ __global__ void __launch_bounds__(64 * PW, EL == 1 ? 4 : 1) k_pair(const SegDev*
             if (p1) {
                 nuj = upos[s1];
                 nmj = umeta[s1];
-                njv = vs[s1];
+                if (MODE == 1) njv = vs[s1];
             }
             r2 = k0 + 16 + rsub < cnt ? (uint32_t)nl[k0 + 16 + rsub] : 0u;
             float jx, jy, jz;
@@ -701,16 +713,17 @@ __global__ void __launch_bounds__(64 * PW, EL == 1 ? 4 : 1) k_pair(const SegDev*
             const int off = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
                                                       __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
             wave_sync();  // the previous reads of the ring are done before it is overwritten
-            if (MODE == 1 && !N3 && pass) {  // full-shell Hessian kernels only
+            if (!N3 && pass) {  // full-shell kernels only
                 const int e = (wp + off) & (RING - 1);
                 ring4[e] = make_float4(jx, jy, jz, QSC * __uint_as_float(uj.w));
-                ring4[RING + e] = make_float4(__int_as_float(mj.x), jv.x, jv.y, jv.z);
+                if (MODE == 1) ring4[RING + e] = make_float4(__int_as_float(mj.x), jv.x, jv.y, jv.z);
+                else ring[4 * RING + e] = __int_as_float(mj.x);
             }
             wp += __popcll(m);
             wave_sync();
-            while (wp - rp >= 64) {
-                eval.template operator()<true>(rp, 64);
-                rp += 64;
+            while (wp - rp >= EB) {
+                eval.template operator()<true>(rp, EB);
+                rp += EB;
                 wave_sync();
             }
         }

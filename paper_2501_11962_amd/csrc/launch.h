@@ -17,8 +17,9 @@ void run_displace(const SegDev* dsegs, const SegDev* hsegs, const Launch& base, 
 // Pair kernels.  mode 0: forces into f32 (outsel 0), hv32 (outsel 1) or f32m (outsel 2);
 // energy_bead: -1 none, -2 every bead, b >= 0 that bead only.  mode 1: H v from vs into hv32.
 // newton3: each pair once with atomics (1) or from both sides without atomics (0).
-// lists: 1 = the force pass records neighbour lists, 2 = the Hessian pass reads them
-// (full-shell kernels of segments with lcap > 0), 0 = neither.
+// lists: 1 = the force pass records neighbour lists, 2 = a later pass over the same
+// binning reads them (the Hessian pass, or the displaced force passes of shared-bin finite
+// differences; full-shell kernels of segments with lcap > 0), 0 = neither.
 void run_pair(const SegDev* dsegs, const SegDev* hsegs, const Launch& base, char* ws, int mode,
               int outsel, int energy_bead, int waves, int newton3, hipStream_t st,
               int lists = 0);

@@ -20,7 +20,10 @@ using namespace mop;
 namespace {
 
 constexpr double F_ELEC = 138.935458;  // kJ mol^-1 nm e^-2
-constexpr double SEARCH_MARGIN = 1.0e-4;  // nm added to the cutoff for neighbour pruning
+// nm added to the cutoff for neighbour pruning; displacements of up to half of it keep a
+// recorded neighbour list exact (the shared-bin finite differences replay the lists of R
+// for R +/- eps d with max |eps d_i| = fd_h)
+constexpr double SEARCH_MARGIN = 2.0e-4;
 constexpr double PI = 3.14159265358979323846;
 constexpr double PME_SPACING = 0.12;      // nm per grid point of the automatic PME grid
 
@@ -979,8 +982,9 @@ static void path_sequence(const SegDev* dsegs, const SegDev* hsegs, const Launch
     // forces of beads 1..N-1 (bead 1 alone for N = 1), energy of bead 1
     run_binning(dsegs, hsegs, base, cp.ws, cp.R, 0, 0.0, st);
     mark(1);
-    // exact gradients: the force pass records neighbour lists for the Hessian pass
-    const int lists = (grad && mode == 0) ? 1 : 0;
+    // exact gradients: the force pass records neighbour lists for the Hessian pass; with
+    // shared-bin finite differences, for the two displaced force passes
+    const int lists = (grad && (mode == 0 || mode == 2)) ? 1 : 0;
     run_pair(dsegs, hsegs, base, cp.ws, 0, 0, 0, waves, n3, st, lists);
     mark(2);
     if (side) join_side(pl, st);
@@ -1012,7 +1016,8 @@ static void path_sequence(const SegDev* dsegs, const SegDev* hsegs, const Launch
             for (int sgn : {+1, -1}) {
                 if (mode == 1) run_binning(dsegs, hsegs, Lh, cp.ws, cp.R, sgn, cp.fd_h, st);
                 else run_displace(dsegs, hsegs, Lh, cp.ws, cp.R, sgn, cp.fd_h, st);
-                run_pair(dsegs, hsegs, Lh, cp.ws, 0, sgn > 0 ? 1 : 2, -1, waves, n3, st);
+                run_pair(dsegs, hsegs, Lh, cp.ws, 0, sgn > 0 ? 1 : 2, -1, waves, n3, st,
+                         mode == 2 ? 2 * lists : 0);
                 if (pme) pme_forces(pl, Lh.nb[0], cp, sgn, sgn > 0 ? 1 : 2, true, st);
             }
         }
