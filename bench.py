@@ -177,7 +177,8 @@ def bench_batch(args, mop, ctx, log):
     tuned = not args.no_autotune
     if tuned:
         from paper_2501_11962_amd import autotune as A
-        space = {k: v for k, v in A.SPACE.items() if k != "waves"}   # one launch shape per batch
+        # a batch takes its launch shape (waves, persistent) from its first plan
+        space = {k: v for k, v in A.SPACE.items() if k not in ("waves", "persistent")}
     for s_, R, seed in batch:
         N = R.shape[0]
         Rs.append(R)

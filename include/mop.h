@@ -138,6 +138,11 @@ typedef struct {
  *               stream in call order instead of on a second stream of the plan beside
  *               the pair kernels.  Results are bit-identical either way; for callers
  *               that need every kernel on one stream, and for timing each kernel alone.
+ *               MOP_PLAN_PERSISTENT: launch the pair kernels as persistent grids (as
+ *               many workgroups as the GPU holds at once, each taking clusters from a
+ *               work queue per XCD until it is empty) instead of one workgroup per
+ *               group of clusters.  Results are bit-identical either way.  A batch
+ *               takes this flag, like waves, from its first plan.
  *   list_cap    neighbour-list records per 8-atom cluster.  veff_grad (exact mode)
  *               records, in its force pass, which atoms passed each cluster's
  *               neighbour search (one 32-bit record per neighbouring cluster with at
@@ -149,6 +154,7 @@ typedef struct {
  */
 #define MOP_PLAN_NEWTON3 1
 #define MOP_PLAN_ONE_STREAM 2
+#define MOP_PLAN_PERSISTENT 4
 typedef struct {
     double col_width;
     double zbin;

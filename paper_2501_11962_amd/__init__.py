@@ -30,6 +30,7 @@ MOP_DEV_OVERLAP = 4
 MOP_STATIC_WORKSPACE_BYTES = 67108864
 MOP_PLAN_NEWTON3 = 1
 MOP_PLAN_ONE_STREAM = 2
+MOP_PLAN_PERSISTENT = 4
 MOP_ELEC_RF, MOP_ELEC_PME = 0, 1
 
 _lib = None
@@ -268,12 +269,13 @@ class Plan:
     """Plan for up to max_beads beads; owns a device workspace (torch uint8)."""
 
     def __init__(self, system, max_beads, col_width=0.0, zbin=0.0, waves=0, newton3=False,
-                 list_cap=0, one_stream=False):
+                 list_cap=0, one_stream=False, persistent=False):
         torch = _torch()
         self.system = system
         self.Q = system.Q
         self.max_beads = int(max_beads)
-        flags = (MOP_PLAN_NEWTON3 if newton3 else 0) | (MOP_PLAN_ONE_STREAM if one_stream else 0)
+        flags = ((MOP_PLAN_NEWTON3 if newton3 else 0) | (MOP_PLAN_ONE_STREAM if one_stream else 0)
+                 | (MOP_PLAN_PERSISTENT if persistent else 0))
         o = _Opts(col_width, zbin, waves, flags, int(list_cap))
         h = C.c_void_p()
         _check(lib().mop_plan_create(system.h, self.max_beads, C.byref(o), C.byref(h)),

@@ -7,7 +7,9 @@ The pair kernels' cost depends on
                tightly each column's z window fits the search sphere),
     waves      waves per workgroup of the pair kernels,
     list_cap   the neighbour lists the force pass records for the Hessian pass
-               (0: sized from the density; -1: none, the Hessian pass searches again).
+               (0: sized from the density; -1: none, the Hessian pass searches again),
+    persistent flat grids (one workgroup per group of clusters) or persistent grids
+               over per-XCD work queues for the pair kernels.
 `autotune` times veff_grad on the caller's own system and path (HIP events on the
 library stream, median of a few calls after a warm-up) and searches the space one
 parameter at a time: starting from the default plan, each sweep tries every value of one
@@ -28,9 +30,9 @@ import os
 
 import numpy as np
 
-DEFAULT = dict(col_width=0.4, zbin=0.1, waves=4, list_cap=0)
+DEFAULT = dict(col_width=0.4, zbin=0.1, waves=4, list_cap=0, persistent=False)
 SPACE = dict(col_width=(0.35, 0.4, 0.45, 0.5), zbin=(0.05, 0.1, 0.2), waves=(2, 4, 8),
-             list_cap=(0, -1))
+             list_cap=(0, -1), persistent=(False, True))
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "mop_autotune.json")
 
 

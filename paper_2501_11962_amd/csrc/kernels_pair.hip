@@ -15,6 +15,8 @@
 //   3. Every EB (64) ring entries, EB/8 steps of 8 j-atoms x 8 i-atoms (lane = 8*i + j)
 //      evaluate the pair terms; each lane accumulates a partial sum for its i atom.
 //   4. Partial sums are reduced over the 8 j lanes.
+// Launch: a flat grid (one workgroup per W clusters, k_pair) or, as a plan option, a
+// persistent grid over per-XCD work queues (k_pair_q); both run the same per-wave body.
 //
 // Two variants:
 //   N3 = 1 (opt-in): Newton's third law.  A wave takes only clusters with a larger
@@ -48,6 +50,7 @@
 // 0 <= x <= 6 (coefficients from erfc_fit.py next to this package; relative error below
 // 4e-7 in FP32), so E and D share one exponential.
 #include <algorithm>
+#include <atomic>
 
 #include "device_common.h"
 #include "launch.h"
@@ -234,28 +237,11 @@ __device__ __forceinline__ void pair_term(const IAtom& I, const PairK& P, const 
     }
 }
 
-template <int MODE, int PW, int N3, int EL>
-__global__ void __launch_bounds__(64 * PW, EL == 1 ? 4 : 1) k_pair(const SegDev* __restrict__ segs, Launch L,
-                                                 char* __restrict__ ws, int outsel, int energy_bead,
-                                                 int lists) {
-    using FL = Fields<MODE, N3>;
-    constexpr int NF = FL::NF, FV = FL::V;
-    extern __shared__ float4 s_dyn[];
-
-    const int nblk = L.pf[L.nseg];
-    const int per = (nblk + 7) >> 3;
-    // consecutive logical blocks (neighbouring clusters) stay on one XCD
-    const int lblk = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
-    if (lblk >= nblk) return;
-    const int p = find_seg(L, lblk);
-    const SegDev* __restrict__ sg = segs + p;
+// Copy segment p's pair table(s) to LDS: threads t0, t0 + stride, ... of the caller's group.
+template <int MODE>
+__device__ __forceinline__ void load_table(const SegDev* __restrict__ sg, float4* s_tab, int t0, int stride) {
     const int nt = sg->s.nt;
-    const int ntm = L.ntmax;
-    constexpr int TC = TAB_COPIES<MODE>;
-    float4* s_tab = s_dyn;
-    float* s_ring = reinterpret_cast<float*>(s_dyn + TC * ntm * ntm);
-    int* s_cl = reinterpret_cast<int*>(s_ring + PW * NF * RING);
-    for (int t = threadIdx.x; t < nt * nt; t += 64 * PW) {
+    for (int t = t0; t < nt * nt; t += stride) {
         if (MODE == 1) {
             s_tab[t] = sg->s.tabh[t];
         } else {
@@ -263,11 +249,21 @@ __global__ void __launch_bounds__(64 * PW, EL == 1 ? 4 : 1) k_pair(const SegDev*
             s_tab[nt * nt + t] = sg->s.tab2[t];
         }
     }
-    __syncthreads();  // the only block barrier: waves are independent from here on
+}
 
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+// The work of one wave: i-cluster gw (bead gw / cpb, cluster gw % cpb) of path p, with the
+// path's table at s_tab and the wave's own ring and candidate list in LDS.
+template <int MODE, int N3, int EL>
+__device__ __forceinline__ void pair_wave(const SegDev* __restrict__ segs, const Launch& L,
+                                          char* __restrict__ ws, int outsel, int energy_bead,
+                                          int lists, int p, int gw, const float4* s_tab,
+                                          float* ring, int* clist) {
+    using FL = Fields<MODE, N3>;
+    constexpr int NF = FL::NF, FV = FL::V;
+    const SegDev* __restrict__ sg = segs + p;
+    const int nt = sg->s.nt;
+    const int lane = threadIdx.x & 63;
     const int cpb = sg->s.cpb;
-    const int gw = (lblk - L.pf[p]) * PW + wave;
     const int b = gw / cpb, c = gw - b * cpb;
     if (b >= L.nb[p]) return;
     const int S = sg->s.S, Q = sg->s.Q, ncol = sg->s.ncol, nzb = sg->s.nzb;
@@ -417,9 +413,7 @@ __global__ void __launch_bounds__(64 * PW, EL == 1 ? 4 : 1) k_pair(const SegDev*
     int wp = 0, rp = 0;  // ring write / read counters (uniform); rp stays a multiple of EB
     int wr = 0;          // neighbour-list records written (force pass)
 
-    float* ring = s_ring + wave * NF * RING;
     float4* ring4 = reinterpret_cast<float4*>(ring);
-    int* clist = s_cl + wave * CLIST;
 
     // neighbour lists (full-shell kernels): the force pass records the slots that pass
     // the search, the Hessian pass of the same bead replays them
@@ -845,6 +839,71 @@ __global__ void __launch_bounds__(64 * PW, EL == 1 ? 4 : 1) k_pair(const SegDev*
     }
 }
 
+// One workgroup per PW i-clusters; consecutive workgroups of the logical order
+// (neighbouring clusters) go to one XCD (workgroups are dealt to the 8 XCDs in turn).
+template <int MODE, int PW, int N3, int EL>
+__global__ void __launch_bounds__(64 * PW, EL == 1 ? 4 : 1) k_pair(const SegDev* __restrict__ segs, Launch L,
+                                                 char* __restrict__ ws, int outsel, int energy_bead,
+                                                 int lists) {
+    constexpr int NF = Fields<MODE, N3>::NF;
+    extern __shared__ float4 s_dyn[];
+    const int nblk = L.pf[L.nseg];
+    const int per = (nblk + 7) >> 3;
+    const int lblk = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+    if (lblk >= nblk) return;
+    const int p = find_seg(L, lblk);
+    float4* s_tab = s_dyn;
+    float* s_ring = reinterpret_cast<float*>(s_dyn + TAB_COPIES<MODE> * L.ntmax * L.ntmax);
+    int* s_cl = reinterpret_cast<int*>(s_ring + PW * NF * RING);
+    load_table<MODE>(segs + p, s_tab, threadIdx.x, 64 * PW);
+    __syncthreads();  // the only block barrier: waves are independent from here on
+    const int wave = threadIdx.x >> 6;
+    pair_wave<MODE, N3, EL>(segs, L, ws, outsel, energy_bead, lists, p, (lblk - L.pf[p]) * PW + wave,
+                            s_tab, s_ring + wave * NF * RING, s_cl + wave * CLIST);
+}
+
+// Persistent form: as many workgroups as the GPU holds at once, each taking logical blocks
+// of PW i-clusters (the flat form's workgroups) from its XCD's queue until the queue is
+// empty; XCD x owns logical blocks x*per .. (x+1)*per - 1, taken in order.  One block
+// barrier per logical block: the taken index goes through two alternating LDS words, so a
+// word is rewritten only after every wave has passed the barrier that follows its next
+// read.  The path's table is reloaded only when the path changes.  queue: 8 counters, zero
+// before the launch.  A block's results do not depend on which workgroup computes it:
+// results equal k_pair's.
+template <int MODE, int PW, int N3, int EL>
+__global__ void __launch_bounds__(64 * PW, 4) k_pair_q(const SegDev* __restrict__ segs, Launch L,
+                                                   char* __restrict__ ws, int outsel, int energy_bead,
+                                                   int lists, int* __restrict__ queue) {
+    constexpr int NF = Fields<MODE, N3>::NF;
+    extern __shared__ float4 s_dyn[];
+    __shared__ int s_next[2];
+    const int nblk = L.pf[L.nseg];
+    const int per = (nblk + 7) >> 3;
+    const int x = (int)(blockIdx.x & 7);
+    const int wave = threadIdx.x >> 6;
+    float4* s_tab = s_dyn;
+    float* s_ring = reinterpret_cast<float*>(s_dyn + TAB_COPIES<MODE> * L.ntmax * L.ntmax);
+    int* s_cl = reinterpret_cast<int*>(s_ring + PW * NF * RING);
+    int cur = -1;
+    for (int it = 0;; it ^= 1) {
+        if (threadIdx.x == 0) s_next[it] = atomicAdd(queue + x, 1);
+        __syncthreads();  // also: every wave is done with the previous block (and table)
+        const int k = s_next[it];
+        const int lblk = x * per + k;
+        if (k >= per || lblk >= nblk) break;
+        const int p = find_seg(L, lblk);
+        if (p != cur) {
+            load_table<MODE>(segs + p, s_tab, threadIdx.x, 64 * PW);
+            __syncthreads();
+            cur = p;
+        }
+        pair_wave<MODE, N3, EL>(segs, L, ws, outsel, energy_bead, lists, p, (lblk - L.pf[p]) * PW + wave,
+                                s_tab, s_ring + wave * NF * RING, s_cl + wave * CLIST);
+    }
+}
+
+__global__ void k_queue_reset(int* queue) { queue[threadIdx.x] = 0; }
+
 // Slot-order sums of the Newton-3 kernel to original atom order (float4), clearing the
 // slot-order buffer for the next pass.
 __global__ void __launch_bounds__(EWB) k_unsort(const SegDev* __restrict__ segs, Launch L, char* ws,
@@ -871,7 +930,7 @@ __global__ void __launch_bounds__(EWB) k_unsort(const SegDev* __restrict__ segs,
 
 template <int MODE, int PW, int N3, int EL>
 static void launch_pair_t(const SegDev* dsegs, const SegDev* hsegs, const Launch& base, char* ws,
-                          int outsel, int energy_bead, int lists, hipStream_t st) {
+                          int outsel, int energy_bead, int lists, bool persistent, hipStream_t st) {
     Launch L = base;
     L.pf[0] = 0;
     L.ntmax = 1;
@@ -881,22 +940,53 @@ static void launch_pair_t(const SegDev* dsegs, const SegDev* hsegs, const Launch
     }
     const int nblk = L.pf[base.nseg];
     if (nblk == 0) return;
-    const int grid = ((nblk + 7) / 8) * 8;
-    const size_t lds = TAB_COPIES<MODE> * (size_t)L.ntmax * L.ntmax * sizeof(float4) +
-                       (size_t)PW * Fields<MODE, N3>::NF * RING * sizeof(float) +
-                       (size_t)PW * CLIST * sizeof(int);
-    hipLaunchKernelGGL((k_pair<MODE, PW, N3, EL>), dim3(grid), dim3(64 * PW), lds, st, dsegs, L, ws,
-                       outsel, energy_bead, lists);
+    const size_t tab = TAB_COPIES<MODE> * (size_t)L.ntmax * L.ntmax * sizeof(float4);
+    const size_t wlds = (size_t)Fields<MODE, N3>::NF * RING * sizeof(float) + CLIST * sizeof(int);
+    if (persistent) {
+        // a grid of what the GPU holds at once: a multiple of 8 workgroups (one set per XCD
+        // queue), no more workgroups than logical blocks
+        const size_t lds = tab + PW * wlds;
+        // CU count and resident workgroups per CU, cached per kernel as (lds << 32 | occ)
+        static std::atomic<int> ncu_c{0};
+        static std::atomic<unsigned long long> occ_c{0};
+        int ncu = ncu_c.load(std::memory_order_relaxed);
+        if (ncu <= 0) {
+            int dev = 0;
+            if (hipGetDevice(&dev) != hipSuccess ||
+                hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+                ncu <= 0)
+                ncu = 256;
+            ncu_c.store(ncu, std::memory_order_relaxed);
+        }
+        unsigned long long oc = occ_c.load(std::memory_order_relaxed);
+        int occ = (int)(oc & 0xFFFFFFFFull);
+        if (occ <= 0 || (oc >> 32) != lds) {
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_pair_q<MODE, PW, N3, EL>, 64 * PW, lds) !=
+                    hipSuccess || occ <= 0)
+                occ = 1;
+            occ_c.store(((unsigned long long)lds << 32) | (unsigned)occ, std::memory_order_relaxed);
+        }
+        const int per = (nblk + 7) / 8;
+        const int wg = std::max(1, std::min(per, occ * ncu / 8));
+        int* queue = reinterpret_cast<int*>(ws + WS_QUEUE);
+        hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(8), 0, st, queue);
+        hipLaunchKernelGGL((k_pair_q<MODE, PW, N3, EL>), dim3(8 * wg), dim3(64 * PW), lds, st, dsegs, L,
+                           ws, outsel, energy_bead, lists, queue);
+        return;
+    }
+    hipLaunchKernelGGL((k_pair<MODE, PW, N3, EL>), dim3(8 * ((nblk + 7) / 8)), dim3(64 * PW),
+                       tab + PW * wlds, st, dsegs, L, ws, outsel, energy_bead, lists);
 }
 
 template <int MODE, int N3, int EL>
 static void launch_pair_w(const SegDev* dsegs, const SegDev* hsegs, const Launch& base, char* ws,
                           int outsel, int energy_bead, int waves, int lists, hipStream_t st) {
-    switch (waves) {
-        case 1: launch_pair_t<MODE, 1, N3, EL>(dsegs, hsegs, base, ws, outsel, energy_bead, lists, st); break;
-        case 2: launch_pair_t<MODE, 2, N3, EL>(dsegs, hsegs, base, ws, outsel, energy_bead, lists, st); break;
-        case 8: launch_pair_t<MODE, 8, N3, EL>(dsegs, hsegs, base, ws, outsel, energy_bead, lists, st); break;
-        default: launch_pair_t<MODE, 4, N3, EL>(dsegs, hsegs, base, ws, outsel, energy_bead, lists, st); break;
+    const bool pq = (waves & WAVES_PERSISTENT) != 0;
+    switch (waves & ~WAVES_PERSISTENT) {
+        case 1: launch_pair_t<MODE, 1, N3, EL>(dsegs, hsegs, base, ws, outsel, energy_bead, lists, pq, st); break;
+        case 2: launch_pair_t<MODE, 2, N3, EL>(dsegs, hsegs, base, ws, outsel, energy_bead, lists, pq, st); break;
+        case 8: launch_pair_t<MODE, 8, N3, EL>(dsegs, hsegs, base, ws, outsel, energy_bead, lists, pq, st); break;
+        default: launch_pair_t<MODE, 4, N3, EL>(dsegs, hsegs, base, ws, outsel, energy_bead, lists, pq, st); break;
     }
 }
 

@@ -721,7 +721,8 @@ static void run_fft(const mop_plan_s* pl, bool forward, void* in, void* out, voi
 int mop_plan_create(mop_system sys, int32_t max_beads, const mop_plan_opts* opts, mop_plan* out) {
     if (!sys || !out || max_beads < 1) return MOP_EINVAL;
     *out = nullptr;
-    if (opts && (opts->flags & ~(MOP_PLAN_NEWTON3 | MOP_PLAN_ONE_STREAM))) return MOP_EINVAL;
+    if (opts && (opts->flags & ~(MOP_PLAN_NEWTON3 | MOP_PLAN_ONE_STREAM | MOP_PLAN_PERSISTENT)))
+        return MOP_EINVAL;
     if (sys->dev.elec == 1 && opts && (opts->flags & MOP_PLAN_NEWTON3)) return MOP_EINVAL;
     int waves = opts && opts->waves ? opts->waves : 4;
     if (waves != 1 && waves != 2 && waves != 4 && waves != 8) return MOP_EINVAL;
@@ -731,7 +732,7 @@ int mop_plan_create(mop_system sys, int32_t max_beads, const mop_plan_opts* opts
     if (!pl) return MOP_ENOMEM;
     pl->sys = sys;
     pl->max_beads = max_beads;
-    pl->waves = waves;
+    pl->waves = waves | ((opts && (opts->flags & MOP_PLAN_PERSISTENT)) ? WAVES_PERSISTENT : 0);
     pl->newton3 = (opts && (opts->flags & MOP_PLAN_NEWTON3)) ? 1 : 0;
     pl->one_stream = (opts && (opts->flags & MOP_PLAN_ONE_STREAM)) ? 1 : 0;
     base_seg(pl->hseg, plan_geometry(sys, opts));

@@ -45,6 +45,8 @@ constexpr int RING = 128;         // j-atom ring per wave (power of two, >= 2*64
 constexpr int CLIST = 256;        // candidate-cluster list per wave
 constexpr int MAXTYPES = 16;      // LJ types (the type fills the low 4 bits of a packed key)
 constexpr int EWB = 256;          // block size of the elementwise kernels
+constexpr int WAVES_PERSISTENT = 0x100;  // or-ed into a plan's waves: persistent pair launches
+constexpr size_t WS_QUEUE = 64;   // workspace byte offset of the 8 work-queue counters
 constexpr int32_t DUMMY_KEY = INT32_MIN;
 
 // Status bits (mirrors MOP_DEV_* of the public header).

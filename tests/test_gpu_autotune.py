@@ -49,7 +49,8 @@ def test_autotune_picks_a_candidate_and_caches_it(mop, tmp_path):
 
 
 def test_searched_plan_is_not_slower_than_default(mop, tmp_path):
-    """Parameter-by-parameter search over column width, z-bin height, waves and lists on
+    """Parameter-by-parameter search over column width, z-bin height, waves, lists and
+    persistent launches on
     the 3,000-atom water box: the chosen plan, timed again independently, is at most 5%
     (timing noise) slower than the default plan, and gives the default's gradient to
     within the parity tolerance."""

@@ -415,14 +415,16 @@ def test_newton3_mode(name, N, mop, ctx):
     assert rel(G2.cpu().numpy(), G) < 1e-6
 
 
-def test_graph_replay_matches_eager(mop, ctx):
+@pytest.mark.parametrize("persistent", [False, True])
+def test_graph_replay_matches_eager(persistent, mop, ctx):
     """The whole veff_grad call captured once and replayed; each replay checked against
-    an eager call, with eager work and synchronisation between replays."""
+    an eager call, with eager work and synchronisation between replays.  Persistent plans
+    put the reset of their work queues into the graph as kernels."""
     import torch
     s = W.cfg2()
     N = 6
     R, _, _ = W.random_walk_path(s, N, 23)
-    plan = mop.Plan(mop.System(ctx, s), N)
+    plan = mop.Plan(mop.System(ctx, s), N, persistent=persistent)
     Rt = cuda(R)
     G = torch.empty_like(Rt)
     v = torch.empty(1, dtype=torch.float64, device=Rt.device)
@@ -588,3 +590,38 @@ def test_neighbour_list_replay_is_exact(name, mop, ctx):
     assert np.array_equal(out[0][0], out[-1][0])
     assert np.array_equal(out[64][0], out[-1][0])
     assert out[0][1] == out[-1][1] == out[64][1]
+
+
+@pytest.mark.parametrize("name,waves", [("water1002_cw03", 4), ("cfg2", 1), ("cfg2", 8)])
+def test_persistent_plan_is_bit_identical(name, waves, mop, ctx):
+    """MOP_PLAN_PERSISTENT launches the pair kernels as resident grids that take clusters
+    from per-XCD work queues: every output (both gradient modes, finite differences on
+    shared bins, bead forces, Hessian-vector products, batches) equals the flat launch's
+    bit for bit, also on a second call (the queues start from zero every launch)."""
+    s = SMALL[name]()
+    N = 5
+    R, _, _ = W.random_walk_path(s, N, 29)
+    Rt = cuda(R)
+    Vt = cuda(np.random.default_rng(6).normal(0.0, 1e-3, R.shape))
+    sysm = mop.System(ctx, s)
+    out = []
+    for persistent in (False, True):
+        plan = mop.Plan(sysm, N, waves=waves, persistent=persistent)
+        res = []
+        for _ in range(2):
+            G, v = mop.veff_grad(plan, Rt)
+            G2, v2 = mop.veff_grad(plan, Rt, mode=2, fd_h=1e-4)
+            F, U = mop.bead_forces(plan, Rt)
+            H = mop.bead_hvp(plan, Rt, Vt)
+            res.append([x.cpu().numpy() for x in (G, v, G2, v2, F, U, H)])
+        assert plan.status() == 0
+        for a, b in zip(*res):
+            assert np.array_equal(a, b)
+        bt = mop.Batch([plan, plan], [N, N - 2])
+        Gb, vb = bt.veff_grad(bt.pack([Rt, Rt[:N - 2].contiguous()]))
+        assert bt.status() == 0
+        res[0] += [Gb.cpu().numpy(), vb.cpu().numpy()]
+        out.append(res[0])
+    for k, (a, b) in enumerate(zip(*out)):
+        assert np.array_equal(a, b), k
+    say(f"[persistent] {name} waves={waves}: {len(out[0])} outputs bit-identical")

@@ -172,14 +172,16 @@ def test_pme_repeated_calls_bit_identical(mop, ctx):
 
 def test_pme_one_stream_plan_is_bit_identical(mop, ctx):
     """MOP_PLAN_ONE_STREAM puts the mesh work on the caller's stream (after the pair
-    kernels) instead of a second stream beside them: every result is bit-identical, in
+    kernels) instead of a second stream beside them, and MOP_PLAN_PERSISTENT launches the
+    pair kernels as resident grids over work queues: every result is bit-identical, in
     both gradient modes and through bead_forces / bead_hvp; unknown plan flags are refused."""
     import ctypes as C
     s = W.with_pme(W.water_box(1002, seed=9, rc=1.0))
     N = 4
     R, _, _ = W.random_walk_path(s, N, 31)
     sysm = mop.System(ctx, s)
-    plans = [mop.Plan(sysm, N), mop.Plan(sysm, N, one_stream=True)]
+    plans = [mop.Plan(sysm, N), mop.Plan(sysm, N, one_stream=True),
+             mop.Plan(sysm, N, persistent=True)]
     Rt = cuda(R)
     Vt = cuda(np.random.default_rng(4).normal(0.0, 1e-3, R.shape))
     out = []
@@ -190,9 +192,9 @@ def test_pme_one_stream_plan_is_bit_identical(mop, ctx):
         H = mop.bead_hvp(pl, Rt, Vt).cpu().numpy()
         assert pl.status() == 0
         out.append((G, v, Gf, vf, F, U, H))
-    for a, b in zip(*out):
-        assert np.array_equal(a, b)
-    o = mop._Opts(0.0, 0.0, 0, 4, 0)
+    for a, b, c in zip(*out):
+        assert np.array_equal(a, b) and np.array_equal(a, c)
+    o = mop._Opts(0.0, 0.0, 0, 8, 0)
     h = C.c_void_p()
     assert mop.lib().mop_plan_create(sysm.h, N, C.byref(o), C.byref(h)) == -1  # MOP_EINVAL
 
