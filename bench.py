@@ -52,6 +52,23 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def settle(fn, calls, seconds=0.3):
+    """Untimed warm-up: at least `calls` calls of fn and at least `seconds` of wall time
+    with the GPU busy.  After a pause (a capture, host work) the GPU clock takes tens of
+    calls to climb back: in a kernel trace the first replays after a capture ran up to 15%
+    slower than the settled ones."""
+    import torch
+    t0 = time.perf_counter()
+    k = 0
+    while k < calls or time.perf_counter() - t0 < seconds:
+        fn()
+        k += 1
+        if k % 4 == 0:
+            torch.cuda.synchronize()
+    torch.cuda.synchronize()
+    return k
+
+
 def unique_pairs(system, X):
     """Unique non-excluded atom pairs closer than the cutoff (minimum image), counted
     with a periodic k-d tree; bonded 1-2/1-3 pairs are always within the cutoff here and
@@ -196,6 +213,7 @@ def bench_batch(args, mop, ctx, log):
     torch.cuda.synchronize()
     if bt.status():
         raise SystemExit(f"batch device status {bt.status()}")
+    settle(lambda: bt.veff_grad(Rf, G=G, veff=v), 1)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(args.steps):
@@ -217,6 +235,7 @@ def bench_batch(args, mop, ctx, log):
         g.replay()
         torch.cuda.synchronize()
         if torch.equal(G, Gref):
+            settle(g.replay, args.warmup)
             e0.record()
             for _ in range(args.steps):
                 g.replay()
@@ -354,6 +373,7 @@ def bench_pme(args, mop, ctx, system, R, ms_rf, npairs, log):
         mop.veff_grad(plan, Rt, 0, 0.0, G, v)
     torch.cuda.synchronize()
     st = plan.status()
+    settle(lambda: mop.veff_grad(plan, Rt, 0, 0.0, G, v), 1)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(args.steps):
@@ -371,6 +391,7 @@ def bench_pme(args, mop, ctx, system, R, ms_rf, npairs, log):
             mop.veff_grad(plan, Rt, 0, 0.0, G, v)
         ctx.set_stream()
         torch.cuda.synchronize()
+        settle(g.replay, args.warmup)
         e0.record()
         for _ in range(args.steps):
             g.replay()
@@ -545,6 +566,7 @@ def main():
 
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     # eager timing
+    settle(step, 0)
     ms_eager, med_eager = timed(step, args.steps)
     log(f"[bench] eager: {ms_eager:.3f} ms/step (median {med_eager:.3f})")
 
@@ -567,8 +589,7 @@ def main():
             if not torch.equal(G, Gref):
                 err = float((G - Gref).norm() / Gref.norm())
                 raise RuntimeError(f"graph replay differs from eager (rel L2 {err:.2e})")
-            for _ in range(3):
-                g.replay()
+            settle(g.replay, max(3, args.warmup))
             ms_graph, med_graph = timed(g.replay, args.steps)
             log(f"[bench] graph: {ms_graph:.3f} ms/step (median {med_graph:.3f})")
         except Exception as ex:  # graph capture is optional; eager timing stands

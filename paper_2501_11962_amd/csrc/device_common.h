@@ -44,6 +44,31 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Value of lane (l ^ M) for lane l of a wave.  M < 32: a swizzle in bit mode (and-mask
+// 0x1F, xor-mask M, within each half of the wave); M == 32: a permute across the halves.
+// Unlike __shfl_xor these need no per-lane bound, which the compiler would otherwise keep
+// in a register for the whole kernel.
+template <int M>
+__device__ __forceinline__ int lane_xor(int v) {
+    static_assert(M > 0 && M <= 32 && (M & (M - 1)) == 0, "lane mask");
+    if constexpr (M < 32) {
+        return __builtin_amdgcn_ds_swizzle(v, 0x1F | (M << 10));
+    } else {
+        const int l = (int)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+        return __builtin_amdgcn_ds_bpermute((l ^ 32) << 2, v);
+    }
+}
+template <int M>
+__device__ __forceinline__ float lane_xor(float v) {
+    return __int_as_float(lane_xor<M>(__float_as_int(v)));
+}
+template <int M>
+__device__ __forceinline__ double lane_xor(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = lane_xor<M>((int)(b & 0xFFFFFFFFll)), hi = lane_xor<M>((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
 __device__ __forceinline__ int wave_incl_scan(int v) {
     const int lane = threadIdx.x & 63;
 #pragma unroll

@@ -51,6 +51,7 @@
 // 4e-7 in FP32), so E and D share one exponential.
 #include <algorithm>
 #include <atomic>
+#include <type_traits>
 
 #include "device_common.h"
 #include "launch.h"
@@ -333,15 +334,18 @@ __device__ __forceinline__ void pair_wave(const SegDev* __restrict__ segs, const
         hiy = I.v ? y : -3.0e38f;
         loz = I.v ? z : 3.0e38f;
         hiz = I.v ? z : -3.0e38f;
-#pragma unroll
-        for (int m = 8; m < 64; m <<= 1) {
-            lox = fminf(lox, __shfl_xor(lox, m, 64));
-            hix = fmaxf(hix, __shfl_xor(hix, m, 64));
-            loy = fminf(loy, __shfl_xor(loy, m, 64));
-            hiy = fmaxf(hiy, __shfl_xor(hiy, m, 64));
-            loz = fminf(loz, __shfl_xor(loz, m, 64));
-            hiz = fmaxf(hiz, __shfl_xor(hiz, m, 64));
-        }
+        auto step = [&](auto mc) __attribute__((always_inline)) {
+            constexpr int M = decltype(mc)::value;
+            lox = fminf(lox, lane_xor<M>(lox));
+            hix = fmaxf(hix, lane_xor<M>(hix));
+            loy = fminf(loy, lane_xor<M>(loy));
+            hiy = fmaxf(hiy, lane_xor<M>(hiy));
+            loz = fminf(loz, lane_xor<M>(loz));
+            hiz = fmaxf(hiz, lane_xor<M>(hiz));
+        };
+        step(std::integral_constant<int, 8>{});
+        step(std::integral_constant<int, 16>{});
+        step(std::integral_constant<int, 32>{});
     };
     bbox((float)(int)(ui.x - ref.x) * sx, (float)(int)(ui.y - ref.y) * sy,
          (float)(int)(ui.z - ref.z) * sz);
@@ -789,7 +793,7 @@ __device__ __forceinline__ void pair_wave(const SegDev* __restrict__ segs, const
         for (;;) {
             const int len = (a1 - a0) + (b1 - b0);
             const int incl = wave_incl_scan(len);
-            const int total = __shfl(incl, 63, 64);
+            const int total = __builtin_amdgcn_readlane(incl, 63);
             if (total == 0) break;
             const int excl = incl - len;
             const int take = min(len, max(0, CLIST - excl));
@@ -812,12 +816,15 @@ __device__ __forceinline__ void pair_wave(const SegDev* __restrict__ segs, const
     if (rec && lane == 0) *nlc = wr;
 
     // ---- reduce over the 8 j lanes of each i atom and store ------------------------
-#pragma unroll
-    for (int m = 1; m < 8; m <<= 1) {
-        ax += __shfl_xor(ax, m, 64);
-        ay += __shfl_xor(ay, m, 64);
-        az += __shfl_xor(az, m, 64);
-    }
+    ax += lane_xor<1>(ax);
+    ay += lane_xor<1>(ay);
+    az += lane_xor<1>(az);
+    ax += lane_xor<2>(ax);
+    ay += lane_xor<2>(ay);
+    az += lane_xor<2>(az);
+    ax += lane_xor<4>(ax);
+    ay += lane_xor<4>(ay);
+    az += lane_xor<4>(az);
     if (jslot == 0 && I.v) {
         if (N3) {
             unsafeAtomicAdd(fsx + si, ax);
@@ -833,16 +840,30 @@ __device__ __forceinline__ void pair_wave(const SegDev* __restrict__ segs, const
     }
     if (wantE) {
         eacc64 += (double)eacc;
-#pragma unroll
-        for (int m = 1; m < 64; m <<= 1) eacc64 += __shfl_xor(eacc64, m, 64);
+        eacc64 += lane_xor<1>(eacc64);
+        eacc64 += lane_xor<2>(eacc64);
+        eacc64 += lane_xor<4>(eacc64);
+        eacc64 += lane_xor<8>(eacc64);
+        eacc64 += lane_xor<16>(eacc64);
+        eacc64 += lane_xor<32>(eacc64);
         if (lane == 0) wsp<double>(ws, sg->o_epart)[(size_t)b * cpb + c] = eacc64;
     }
 }
 
+// Waves per SIMD the pair kernels are compiled for (register budget 512 / waves, in
+// steps of 8): 5 (96 registers), and 6 (80) for the full-shell reaction-field Hessian
+// kernel; all flat-grid kernels fit without spills.  Measured per veff_grad call against 4 waves (128 registers): -7.5% on
+// the 150,000-atom reaction-field workload and -1.5% with particle-mesh Ewald.  The wave
+// index is made scalar (readfirstlane) and the lane exchanges use swizzles (lane_xor), so
+// that per-wave pointers and shuffle bounds do not occupy vector registers; before that,
+// 5 waves cost 16 spilled registers and 1.1 GB of scratch traffic per force pass.
+template <int MODE, int N3, int EL>
+constexpr int PAIR_WAVES = MODE == 1 && N3 == 0 && EL == 0 ? 6 : 5;
+
 // One workgroup per PW i-clusters; consecutive workgroups of the logical order
 // (neighbouring clusters) go to one XCD (workgroups are dealt to the 8 XCDs in turn).
 template <int MODE, int PW, int N3, int EL>
-__global__ void __launch_bounds__(64 * PW, EL == 1 ? 4 : 1) k_pair(const SegDev* __restrict__ segs, Launch L,
+__global__ void __launch_bounds__(64 * PW, (PAIR_WAVES<MODE, N3, EL>)) k_pair(const SegDev* __restrict__ segs, Launch L,
                                                  char* __restrict__ ws, int outsel, int energy_bead,
                                                  int lists) {
     constexpr int NF = Fields<MODE, N3>::NF;
@@ -857,7 +878,7 @@ __global__ void __launch_bounds__(64 * PW, EL == 1 ? 4 : 1) k_pair(const SegDev*
     int* s_cl = reinterpret_cast<int*>(s_ring + PW * NF * RING);
     load_table<MODE>(segs + p, s_tab, threadIdx.x, 64 * PW);
     __syncthreads();  // the only block barrier: waves are independent from here on
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: scalar indices
     pair_wave<MODE, N3, EL>(segs, L, ws, outsel, energy_bead, lists, p, (lblk - L.pf[p]) * PW + wave,
                             s_tab, s_ring + wave * NF * RING, s_cl + wave * CLIST);
 }
@@ -871,7 +892,7 @@ __global__ void __launch_bounds__(64 * PW, EL == 1 ? 4 : 1) k_pair(const SegDev*
 // before the launch.  A block's results do not depend on which workgroup computes it:
 // results equal k_pair's.
 template <int MODE, int PW, int N3, int EL>
-__global__ void __launch_bounds__(64 * PW, 4) k_pair_q(const SegDev* __restrict__ segs, Launch L,
+__global__ void __launch_bounds__(64 * PW, (PAIR_WAVES<MODE, N3, EL>)) k_pair_q(const SegDev* __restrict__ segs, Launch L,
                                                    char* __restrict__ ws, int outsel, int energy_bead,
                                                    int lists, int* __restrict__ queue) {
     constexpr int NF = Fields<MODE, N3>::NF;
@@ -880,7 +901,7 @@ __global__ void __launch_bounds__(64 * PW, 4) k_pair_q(const SegDev* __restrict_
     const int nblk = L.pf[L.nseg];
     const int per = (nblk + 7) >> 3;
     const int x = (int)(blockIdx.x & 7);
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: scalar indices
     float4* s_tab = s_dyn;
     float* s_ring = reinterpret_cast<float*>(s_dyn + TAB_COPIES<MODE> * L.ntmax * L.ntmax);
     int* s_cl = reinterpret_cast<int*>(s_ring + PW * NF * RING);
