@@ -79,10 +79,29 @@ __device__ __forceinline__ int wave_incl_scan(int v) {
     return v;
 }
 
+// Sum over the 64 lanes of a wave (pairwise: lanes 32 apart first, then 16, ..., 1).
+__device__ __forceinline__ double wave_sum(double v) {
+    v += lane_xor<32>(v);
+    v += lane_xor<16>(v);
+    v += lane_xor<8>(v);
+    v += lane_xor<4>(v);
+    v += lane_xor<2>(v);
+    v += lane_xor<1>(v);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+    v = fmax(v, lane_xor<32>(v));
+    v = fmax(v, lane_xor<16>(v));
+    v = fmax(v, lane_xor<8>(v));
+    v = fmax(v, lane_xor<4>(v));
+    v = fmax(v, lane_xor<2>(v));
+    v = fmax(v, lane_xor<1>(v));
+    return v;
+}
+
 // Block-wide sum of a double (blockDim.x == EWB), result valid in thread 0.
 __device__ __forceinline__ double block_sum(double v, double* sh) {
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+    v = wave_sum(v);
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     __syncthreads();
     if (lane == 0) sh[w] = v;
@@ -95,8 +114,7 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 
 // Block-wide max of a double (blockDim.x == EWB), result valid in thread 0.
 __device__ __forceinline__ double block_max(double v, double* sh) {
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) v = fmax(v, __shfl_xor(v, m, 64));
+    v = wave_max(v);
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     __syncthreads();
     if (lane == 0) sh[w] = v;

@@ -248,9 +248,7 @@ __global__ void __launch_bounds__(EWB) k_overlap(const SegDev* __restrict__ segs
     if (si >= cs[sg.s.ncol] || mi.x == DUMMY_KEY) return;
     const uint4 ui = up[si];
     const int ki = mi.x >> 4;
-    // OVERLAP_R in fixed-point units per axis, rounded up, plus one unit of margin
-    uint32_t dr[3];
-    for (int a = 0; a < 3; ++a) dr[a] = (uint32_t)ceil(OVERLAP_R / sg.s.L[a] * 4294967296.0) + 1u;
+    const uint32_t* dr = sg.s.ovr;  // OVERLAP_R in fixed-point units per axis, with margin
     const int x0 = fixed_bin(ui.x - dr[0], ncx), x1 = fixed_bin(ui.x + dr[0], ncx);
     const int y0 = fixed_bin(ui.y - dr[1], ncy), y1 = fixed_bin(ui.y + dr[1], ncy);
     const int z0 = fixed_bin(ui.z - dr[2], nzb), z1 = fixed_bin(ui.z + dr[2], nzb);

@@ -252,12 +252,14 @@ __device__ __forceinline__ void load_table(const SegDev* __restrict__ sg, float4
     }
 }
 
-// The work of one wave: i-cluster gw (bead gw / cpb, cluster gw % cpb) of path p, with the
-// path's table at s_tab and the wave's own ring and candidate list in LDS.
-template <int MODE, int N3, int EL>
+// The work of one wave: i-cluster gw of path p (bead bead0 + gw / cpb, cluster gw % cpb),
+// with the path's table at s_tab and the wave's own ring and candidate list in LDS.
+// ENERGY: the kernel can sum pair energies (of bead energy_bead, or of every bead for -2);
+// kernels without it need fewer registers.
+template <int MODE, int N3, int EL, int ENERGY>
 __device__ __forceinline__ void pair_wave(const SegDev* __restrict__ segs, const Launch& L,
                                           char* __restrict__ ws, int outsel, int energy_bead,
-                                          int lists, int p, int gw, const float4* s_tab,
+                                          int lists, int bead0, int p, int gw, const float4* s_tab,
                                           float* ring, int* clist) {
     using FL = Fields<MODE, N3>;
     constexpr int NF = FL::NF, FV = FL::V;
@@ -265,8 +267,9 @@ __device__ __forceinline__ void pair_wave(const SegDev* __restrict__ segs, const
     const int nt = sg->s.nt;
     const int lane = threadIdx.x & 63;
     const int cpb = sg->s.cpb;
-    const int b = gw / cpb, c = gw - b * cpb;
-    if (b >= L.nb[p]) return;
+    const int bl = gw / cpb, c = gw - bl * cpb;
+    if (bl >= L.nb[p]) return;
+    const int b = bead0 + bl;
     const int S = sg->s.S, Q = sg->s.Q, ncol = sg->s.ncol, nzb = sg->s.nzb;
     const int ncx = sg->s.ncx, ncy = sg->s.ncy;
     const uint4* __restrict__ upos = wsp<const uint4>(ws, sg->o_upos) + (size_t)b * S;
@@ -280,7 +283,7 @@ __device__ __forceinline__ void pair_wave(const SegDev* __restrict__ segs, const
     const int nslots = colstart[ncol];
     if (c * CLUSTER >= nslots) return;
 
-    const bool wantE = MODE == 0 && (energy_bead == -2 || energy_bead == b);
+    const bool wantE = MODE == 0 && ENERGY && (energy_bead == -2 || energy_bead == b);
     PairK P;
     P.sx = sg->s.sc[0];
     P.sy = sg->s.sc[1];
@@ -851,21 +854,23 @@ __device__ __forceinline__ void pair_wave(const SegDev* __restrict__ segs, const
 }
 
 // Waves per SIMD the pair kernels are compiled for (register budget 512 / waves, in
-// steps of 8): 5 (96 registers), and 6 (80) for the full-shell reaction-field Hessian
-// kernel; all flat-grid kernels fit without spills.  Measured per veff_grad call against 4 waves (128 registers): -7.5% on
-// the 150,000-atom reaction-field workload and -1.5% with particle-mesh Ewald.  The wave
-// index is made scalar (readfirstlane) and the lane exchanges use swizzles (lane_xor), so
-// that per-wave pointers and shuffle bounds do not occupy vector registers; before that,
-// 5 waves cost 16 spilled registers and 1.1 GB of scratch traffic per force pass.
-template <int MODE, int N3, int EL>
-constexpr int PAIR_WAVES = MODE == 1 && N3 == 0 && EL == 0 ? 6 : 5;
+// steps of 8): 6 (80 registers) for the reaction-field force kernel without energies and
+// the full-shell reaction-field Hessian kernel, 5 (96) for the rest; every flat-grid
+// kernel fits without spills.  Measured per veff_grad call on the 150,000-atom workload
+// against 4 waves (128 registers): -7.5% with reaction field, -1.5% with particle-mesh
+// Ewald (whose mesh kernels on the second stream need room beside the pair kernels).  The
+// wave index is made scalar (readfirstlane) and the lane exchanges use swizzles
+// (lane_xor), so that per-wave pointers and shuffle bounds take no vector registers.
+template <int MODE, int N3, int EL, int WE>
+constexpr int PAIR_WAVES = EL == 0 && N3 == 0 && (MODE == 1 || WE == 0) ? 6 : 5;
 
 // One workgroup per PW i-clusters; consecutive workgroups of the logical order
 // (neighbouring clusters) go to one XCD (workgroups are dealt to the 8 XCDs in turn).
-template <int MODE, int PW, int N3, int EL>
-__global__ void __launch_bounds__(64 * PW, (PAIR_WAVES<MODE, N3, EL>)) k_pair(const SegDev* __restrict__ segs, Launch L,
-                                                 char* __restrict__ ws, int outsel, int energy_bead,
-                                                 int lists) {
+// The launch covers beads bead0 .. bead0 + L.nb[p] - 1 of every path p.
+template <int MODE, int PW, int N3, int EL, int WE>
+__global__ void __launch_bounds__(64 * PW, (PAIR_WAVES<MODE, N3, EL, WE>))
+    k_pair(const SegDev* __restrict__ segs, Launch L, char* __restrict__ ws, int outsel,
+           int energy_bead, int lists, int bead0) {
     constexpr int NF = Fields<MODE, N3>::NF;
     extern __shared__ float4 s_dyn[];
     const int nblk = L.pf[L.nseg];
@@ -879,8 +884,9 @@ __global__ void __launch_bounds__(64 * PW, (PAIR_WAVES<MODE, N3, EL>)) k_pair(co
     load_table<MODE>(segs + p, s_tab, threadIdx.x, 64 * PW);
     __syncthreads();  // the only block barrier: waves are independent from here on
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: scalar indices
-    pair_wave<MODE, N3, EL>(segs, L, ws, outsel, energy_bead, lists, p, (lblk - L.pf[p]) * PW + wave,
-                            s_tab, s_ring + wave * NF * RING, s_cl + wave * CLIST);
+    pair_wave<MODE, N3, EL, WE>(segs, L, ws, outsel, energy_bead, lists, bead0, p,
+                                (lblk - L.pf[p]) * PW + wave, s_tab, s_ring + wave * NF * RING,
+                                s_cl + wave * CLIST);
 }
 
 // Persistent form: as many workgroups as the GPU holds at once, each taking logical blocks
@@ -891,10 +897,10 @@ __global__ void __launch_bounds__(64 * PW, (PAIR_WAVES<MODE, N3, EL>)) k_pair(co
 // read.  The path's table is reloaded only when the path changes.  queue: 8 counters, zero
 // before the launch.  A block's results do not depend on which workgroup computes it:
 // results equal k_pair's.
-template <int MODE, int PW, int N3, int EL>
-__global__ void __launch_bounds__(64 * PW, (PAIR_WAVES<MODE, N3, EL>)) k_pair_q(const SegDev* __restrict__ segs, Launch L,
-                                                   char* __restrict__ ws, int outsel, int energy_bead,
-                                                   int lists, int* __restrict__ queue) {
+template <int MODE, int PW, int N3, int EL, int WE>
+__global__ void __launch_bounds__(64 * PW, (PAIR_WAVES<MODE, N3, EL, WE>))
+    k_pair_q(const SegDev* __restrict__ segs, Launch L, char* __restrict__ ws, int outsel,
+             int energy_bead, int lists, int bead0, int* __restrict__ queue) {
     constexpr int NF = Fields<MODE, N3>::NF;
     extern __shared__ float4 s_dyn[];
     __shared__ int s_next[2];
@@ -918,8 +924,9 @@ __global__ void __launch_bounds__(64 * PW, (PAIR_WAVES<MODE, N3, EL>)) k_pair_q(
             __syncthreads();
             cur = p;
         }
-        pair_wave<MODE, N3, EL>(segs, L, ws, outsel, energy_bead, lists, p, (lblk - L.pf[p]) * PW + wave,
-                                s_tab, s_ring + wave * NF * RING, s_cl + wave * CLIST);
+        pair_wave<MODE, N3, EL, WE>(segs, L, ws, outsel, energy_bead, lists, bead0, p,
+                                    (lblk - L.pf[p]) * PW + wave, s_tab, s_ring + wave * NF * RING,
+                                    s_cl + wave * CLIST);
     }
 }
 
@@ -949,9 +956,11 @@ __global__ void __launch_bounds__(EWB) k_unsort(const SegDev* __restrict__ segs,
     wsp<float4>(ws, o)[(size_t)b * Q + i] = v;
 }
 
-template <int MODE, int PW, int N3, int EL>
+// Beads bead0 .. bead0 + base.nb[p] - 1 of every path p.
+template <int MODE, int PW, int N3, int EL, int WE>
 static void launch_pair_t(const SegDev* dsegs, const SegDev* hsegs, const Launch& base, char* ws,
-                          int outsel, int energy_bead, int lists, bool persistent, hipStream_t st) {
+                          int outsel, int energy_bead, int lists, int bead0, bool persistent,
+                          hipStream_t st) {
     Launch L = base;
     L.pf[0] = 0;
     L.ntmax = 1;
@@ -982,8 +991,9 @@ static void launch_pair_t(const SegDev* dsegs, const SegDev* hsegs, const Launch
         unsigned long long oc = occ_c.load(std::memory_order_relaxed);
         int occ = (int)(oc & 0xFFFFFFFFull);
         if (occ <= 0 || (oc >> 32) != lds) {
-            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_pair_q<MODE, PW, N3, EL>, 64 * PW, lds) !=
-                    hipSuccess || occ <= 0)
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_pair_q<MODE, PW, N3, EL, WE>, 64 * PW,
+                                                            lds) != hipSuccess ||
+                occ <= 0)
                 occ = 1;
             occ_c.store(((unsigned long long)lds << 32) | (unsigned)occ, std::memory_order_relaxed);
         }
@@ -991,12 +1001,33 @@ static void launch_pair_t(const SegDev* dsegs, const SegDev* hsegs, const Launch
         const int wg = std::max(1, std::min(per, occ * ncu / 8));
         int* queue = reinterpret_cast<int*>(ws + WS_QUEUE);
         hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(8), 0, st, queue);
-        hipLaunchKernelGGL((k_pair_q<MODE, PW, N3, EL>), dim3(8 * wg), dim3(64 * PW), lds, st, dsegs, L,
-                           ws, outsel, energy_bead, lists, queue);
+        hipLaunchKernelGGL((k_pair_q<MODE, PW, N3, EL, WE>), dim3(8 * wg), dim3(64 * PW), lds, st, dsegs,
+                           L, ws, outsel, energy_bead, lists, bead0, queue);
         return;
     }
-    hipLaunchKernelGGL((k_pair<MODE, PW, N3, EL>), dim3(8 * ((nblk + 7) / 8)), dim3(64 * PW),
-                       tab + PW * wlds, st, dsegs, L, ws, outsel, energy_bead, lists);
+    hipLaunchKernelGGL((k_pair<MODE, PW, N3, EL, WE>), dim3(8 * ((nblk + 7) / 8)), dim3(64 * PW),
+                       tab + PW * wlds, st, dsegs, L, ws, outsel, energy_bead, lists, bead0);
+}
+
+template <int MODE, int PW, int N3, int EL>
+static void launch_pair_e(const SegDev* dsegs, const SegDev* hsegs, const Launch& base, char* ws,
+                          int outsel, int energy_bead, int lists, bool pq, hipStream_t st) {
+    if constexpr (MODE == 1) {
+        launch_pair_t<MODE, PW, N3, EL, 0>(dsegs, hsegs, base, ws, outsel, energy_bead, lists, 0, pq, st);
+    } else if (energy_bead == -1) {
+        launch_pair_t<MODE, PW, N3, EL, 0>(dsegs, hsegs, base, ws, outsel, energy_bead, lists, 0, pq, st);
+    } else if (energy_bead == 0) {
+        // bead 0 of every path with energies, the other beads without (more waves per SIMD)
+        Launch L0 = base, L1 = base;
+        for (int p = 0; p < base.nseg; ++p) {
+            L0.nb[p] = std::min(base.nb[p], 1);
+            L1.nb[p] = base.nb[p] - L0.nb[p];
+        }
+        launch_pair_t<MODE, PW, N3, EL, 1>(dsegs, hsegs, L0, ws, outsel, energy_bead, lists, 0, pq, st);
+        launch_pair_t<MODE, PW, N3, EL, 0>(dsegs, hsegs, L1, ws, outsel, energy_bead, lists, 1, pq, st);
+    } else {
+        launch_pair_t<MODE, PW, N3, EL, 1>(dsegs, hsegs, base, ws, outsel, energy_bead, lists, 0, pq, st);
+    }
 }
 
 template <int MODE, int N3, int EL>
@@ -1004,10 +1035,10 @@ static void launch_pair_w(const SegDev* dsegs, const SegDev* hsegs, const Launch
                           int outsel, int energy_bead, int waves, int lists, hipStream_t st) {
     const bool pq = (waves & WAVES_PERSISTENT) != 0;
     switch (waves & ~WAVES_PERSISTENT) {
-        case 1: launch_pair_t<MODE, 1, N3, EL>(dsegs, hsegs, base, ws, outsel, energy_bead, lists, pq, st); break;
-        case 2: launch_pair_t<MODE, 2, N3, EL>(dsegs, hsegs, base, ws, outsel, energy_bead, lists, pq, st); break;
-        case 8: launch_pair_t<MODE, 8, N3, EL>(dsegs, hsegs, base, ws, outsel, energy_bead, lists, pq, st); break;
-        default: launch_pair_t<MODE, 4, N3, EL>(dsegs, hsegs, base, ws, outsel, energy_bead, lists, pq, st); break;
+        case 1: launch_pair_e<MODE, 1, N3, EL>(dsegs, hsegs, base, ws, outsel, energy_bead, lists, pq, st); break;
+        case 2: launch_pair_e<MODE, 2, N3, EL>(dsegs, hsegs, base, ws, outsel, energy_bead, lists, pq, st); break;
+        case 8: launch_pair_e<MODE, 8, N3, EL>(dsegs, hsegs, base, ws, outsel, energy_bead, lists, pq, st); break;
+        default: launch_pair_e<MODE, 4, N3, EL>(dsegs, hsegs, base, ws, outsel, energy_bead, lists, pq, st); break;
     }
 }
 

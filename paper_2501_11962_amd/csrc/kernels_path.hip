@@ -31,9 +31,10 @@ __device__ __forceinline__ void add_mesh(const SegDev& sg, char* ws, size_t off,
     v[2] += m[2];
 }
 
+// want_dmax: also the per-bead max |d|^2 (finite-difference step, PME dipole-grid scale).
 __global__ void __launch_bounds__(EWB) k_resid(const SegDev* __restrict__ segs, Launch L,
-                                               CallPtrs cp) {
-    __shared__ double sh[EWB / 64];
+                                               CallPtrs cp, int want_dmax) {
+    __shared__ double sh[3][EWB / 64];
     const int blk = blockIdx.x;
     const int p = find_seg(L, blk);
     const SegDev& sg = segs[p];
@@ -72,15 +73,28 @@ __global__ void __launch_bounds__(EWB) k_resid(const SegDev* __restrict__ segs, 
             flag(cp.status, ST_NONFINITE);
         }
     }
-    const double ses = block_sum(es, sh);
-    const double seb = block_sum(eb, sh);
-    const double smax = block_max(d2max, sh);
+    // the three block reductions share one barrier (same summation order as block_sum)
+    es = wave_sum(es);
+    eb = wave_sum(eb);
+    d2max = wave_max(d2max);
+    if ((threadIdx.x & 63) == 0) {
+        sh[0][threadIdx.x >> 6] = es;
+        sh[1][threadIdx.x >> 6] = eb;
+        sh[2][threadIdx.x >> 6] = d2max;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
+        double ses = 0.0, seb = 0.0, smax = 0.0;
+        for (int k = 0; k < EWB / 64; ++k) {
+            ses += sh[0][k];
+            seb += sh[1][k];
+            smax = fmax(smax, sh[2][k]);
+        }
         double* rp = wsp<double>(ws, sg.o_rpart) + 2 * ((size_t)n * sg.bpb + bi);
         rp[0] = ses;
         rp[1] = seb;
         // non-negative doubles order like their bit patterns
-        if (n < N - 1)
+        if (want_dmax && n < N - 1)
             atomicMax(wsp<unsigned long long>(ws, sg.o_dmax) + n,
                       (unsigned long long)__double_as_longlong(smax));
     }
@@ -173,8 +187,7 @@ __device__ double pme_energy_of_bead(const SegDev& sg, char* ws, int b, int t0, 
 // Block-wide sum over RVB threads (result valid in thread 0).
 constexpr int RVB = 1024;
 __device__ __forceinline__ double block_sum_rvb(double v, double* sh) {
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+    v = wave_sum(v);
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     __syncthreads();
     if (lane == 0) sh[w] = v;
@@ -316,9 +329,9 @@ static Launch per_bead_blocks(const Launch& base, const SegDev* hsegs, bool resi
 }
 
 void run_resid(const SegDev* dsegs, const SegDev* hsegs, const Launch& base, const CallPtrs& cp,
-               hipStream_t st) {
+               int want_dmax, hipStream_t st) {
     const Launch L = per_bead_blocks(base, hsegs, true, false);
-    hipLaunchKernelGGL(k_resid, dim3(L.pf[L.nseg]), dim3(EWB), 0, st, dsegs, L, cp);
+    hipLaunchKernelGGL(k_resid, dim3(L.pf[L.nseg]), dim3(EWB), 0, st, dsegs, L, cp, want_dmax);
 }
 
 void run_assemble(const SegDev* dsegs, const SegDev* hsegs, const Launch& base, const CallPtrs& cp,

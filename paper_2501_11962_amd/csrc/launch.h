@@ -26,7 +26,7 @@ void run_pair(const SegDev* dsegs, const SegDev* hsegs, const Launch& base, char
 
 // FP64 path kernels.
 void run_resid(const SegDev* dsegs, const SegDev* hsegs, const Launch& base, const CallPtrs& cp,
-               hipStream_t st);
+               int want_dmax, hipStream_t st);
 void run_assemble(const SegDev* dsegs, const SegDev* hsegs, const Launch& base, const CallPtrs& cp,
                   int fd, hipStream_t st);
 void run_reduce_veff(const SegDev* dsegs, const SegDev* hsegs, const Launch& base,

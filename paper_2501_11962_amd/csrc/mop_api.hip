@@ -358,6 +358,7 @@ static SysDev plan_geometry(const mop_system_s* sys, const mop_plan_opts* opts) 
         s.L[a] = L[a];
         s.Lf[a] = (float)L[a];
         s.sc[a] = (float)(L[a] / 4294967296.0);
+        s.ovr[a] = (uint32_t)std::min(std::ceil(OVERLAP_R / L[a] * 4294967296.0) + 1.0, 4294967295.0);
     }
     s.cw[0] = (float)cwx;
     s.cw[1] = (float)cwy;
@@ -991,7 +992,8 @@ static void path_sequence(const SegDev* dsegs, const SegDev* hsegs, const Launch
     if (side) join_side(pl, st);
     else if (pme) pme_forces(pl, base.nb[0], cp, 0, 3, true, st);
     mark(3);
-    run_resid(dsegs, hsegs, base, cp, st);
+    // max |d|^2 per bead: the finite-difference steps and the PME dipole-grid scale
+    run_resid(dsegs, hsegs, base, cp, grad && (mode != 0 || pme), st);
     mark(4);
     if (grad) {
         Launch Lh = base;

@@ -72,6 +72,7 @@ struct SysDev {
     float sc[3];      // nm per fixed-point unit: L / 2^32
     float Lf[3];
     float cw[2];      // column widths (nm)
+    uint32_t ovr[3];  // OVERLAP_R in fixed-point units per axis, rounded up, plus one
     float rc2;        // cutoff^2
     float rcs;        // neighbour-search radius (cutoff + margin)
     float rcs2;
