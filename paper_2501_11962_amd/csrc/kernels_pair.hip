@@ -1016,8 +1016,9 @@ static void launch_pair_e(const SegDev* dsegs, const SegDev* hsegs, const Launch
         launch_pair_t<MODE, PW, N3, EL, 0>(dsegs, hsegs, base, ws, outsel, energy_bead, lists, 0, pq, st);
     } else if (energy_bead == -1) {
         launch_pair_t<MODE, PW, N3, EL, 0>(dsegs, hsegs, base, ws, outsel, energy_bead, lists, 0, pq, st);
-    } else if (energy_bead == 0) {
-        // bead 0 of every path with energies, the other beads without (more waves per SIMD)
+    } else if (energy_bead == 0 && EL == 0) {
+        // bead 0 of every path with energies, the other beads without (6 waves per SIMD
+        // instead of 5; the Ewald kernels run at 5 either way, so they keep one launch)
         Launch L0 = base, L1 = base;
         for (int p = 0; p < base.nseg; ++p) {
             L0.nb[p] = std::min(base.nb[p], 1);
