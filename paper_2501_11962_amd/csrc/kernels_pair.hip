@@ -1009,6 +1009,14 @@ static void launch_pair_t(const SegDev* dsegs, const SegDev* hsegs, const Launch
                        tab + PW * wlds, st, dsegs, L, ws, outsel, energy_bead, lists, bead0);
 }
 
+// Waves (i-clusters) of a pair launch over every bead of base.
+static long long pair_waves(const SegDev* hsegs, const Launch& base) {
+    long long n = 0;
+    for (int p = 0; p < base.nseg; ++p) n += (long long)base.nb[p] * hsegs[p].s.cpb;
+    return n;
+}
+constexpr long long SPLIT_MIN_WAVES = 16384;  // about 2 rounds of the GPU's resident waves
+
 template <int MODE, int PW, int N3, int EL>
 static void launch_pair_e(const SegDev* dsegs, const SegDev* hsegs, const Launch& base, char* ws,
                           int outsel, int energy_bead, int lists, bool pq, hipStream_t st) {
@@ -1016,9 +1024,10 @@ static void launch_pair_e(const SegDev* dsegs, const SegDev* hsegs, const Launch
         launch_pair_t<MODE, PW, N3, EL, 0>(dsegs, hsegs, base, ws, outsel, energy_bead, lists, 0, pq, st);
     } else if (energy_bead == -1) {
         launch_pair_t<MODE, PW, N3, EL, 0>(dsegs, hsegs, base, ws, outsel, energy_bead, lists, 0, pq, st);
-    } else if (energy_bead == 0 && EL == 0) {
+    } else if (energy_bead == 0 && EL == 0 && pair_waves(hsegs, base) >= SPLIT_MIN_WAVES) {
         // bead 0 of every path with energies, the other beads without (6 waves per SIMD
-        // instead of 5; the Ewald kernels run at 5 either way, so they keep one launch)
+        // instead of 5; the Ewald kernels run at 5 either way, so they keep one launch;
+        // launches too small to fill the GPU gain nothing from a second launch)
         Launch L0 = base, L1 = base;
         for (int p = 0; p < base.nseg; ++p) {
             L0.nb[p] = std::min(base.nb[p], 1);
