@@ -592,14 +592,16 @@ def test_neighbour_list_replay_is_exact(name, mop, ctx):
     assert out[0][1] == out[-1][1] == out[64][1]
 
 
-@pytest.mark.parametrize("name,waves", [("water1002_cw03", 4), ("cfg2", 1), ("cfg2", 8)])
-def test_persistent_plan_is_bit_identical(name, waves, mop, ctx):
+@pytest.mark.parametrize("name,waves,N", [("water1002_cw03", 4, 5), ("cfg2", 1, 5), ("cfg2", 8, 5),
+                                          ("water30000", 4, 6)])
+def test_persistent_plan_is_bit_identical(name, waves, N, mop, ctx):
     """MOP_PLAN_PERSISTENT launches the pair kernels as resident grids that take clusters
     from per-XCD work queues: every output (both gradient modes, finite differences on
     shared bins, bead forces, Hessian-vector products, batches) equals the flat launch's
-    bit for bit, also on a second call (the queues start from zero every launch)."""
-    s = SMALL[name]()
-    N = 5
+    bit for bit, also on a second call (the queues start from zero every launch).  The
+    30,000-atom path is large enough (over 16,384 clusters per pass) for the force pass to
+    run as two launches, bead 1 with energies and the others without."""
+    s = W.water_box(30000, seed=3, rc=1.0) if name == "water30000" else SMALL[name]()
     R, _, _ = W.random_walk_path(s, N, 29)
     Rt = cuda(R)
     Vt = cuda(np.random.default_rng(6).normal(0.0, 1e-3, R.shape))
@@ -617,6 +619,13 @@ def test_persistent_plan_is_bit_identical(name, waves, mop, ctx):
         assert plan.status() == 0
         for a, b in zip(*res):
             assert np.array_equal(a, b)
+        # U(R^1) of veff_energy (the force pass of a path: bead 1 in the energy launch) and
+        # of bead_forces (every bead with energies): same pair sums, bonds summed apart
+        e = mop.veff_energy(plan, Rt).cpu().numpy()
+        U0 = res[0][5][0]
+        assert abs(e[1] - U0) <= 1e-12 * abs(U0), (e[1], U0)
+        assert abs(e[0] - (e[1] + e[2])) <= 1e-12 * abs(e[0])
+        assert float(res[0][1][0]) == e[0]
         bt = mop.Batch([plan, plan], [N, N - 2])
         Gb, vb = bt.veff_grad(bt.pack([Rt, Rt[:N - 2].contiguous()]))
         assert bt.status() == 0
