@@ -21,16 +21,16 @@
 // Two variants:
 //   N3 = 1 (opt-in): Newton's third law.  A wave takes only clusters with a larger
 //      index than its own, so every pair of distinct clusters is evaluated once.  The
-//      j-side contribution of a step is added to the ring entry with an LDS atomic and,
-//      once per EB entries, flushed to a slot-order FP32 buffer with one global atomic
-//      per entry; i-sums are added the same way.  The own cluster is one 8 x 8 block
-//      evaluated from both sides.  Summation order depends on scheduling.
+//      j-side contribution of a step is summed over the 8 i lanes (lane exchanges) and
+//      added to its ring entry by one lane, and, once per EB entries, flushed to a
+//      slot-order FP32 buffer with one global atomic per entry and component; i-sums are
+//      added the same way.  The own cluster is one 8 x 8 block evaluated from both
+//      sides.  Summation order depends on scheduling.
 //   N3 = 0 (default): every pair evaluated from both sides; no atomics; run-to-run
 //      reproducible for a given binning.  Results go straight to original atom order.
-//      Measured on MI355X (150,000 atoms, 15 beads), this is the faster variant: the LDS
-//      atomics of N3 (8 lanes on one address) serialise, and the global flush of the
-//      j-side sums (three float atomics per entry) costs about as much as the pair work
-//      it saves.
+//      Measured on MI355X (150,000 atoms, 15 beads), this is the faster variant: the
+//      global flush of the j-side sums (three float atomics per ring entry) costs more
+//      than the pair work it saves.
 //
 // Pair terms, d = x_j - x_i, r = |d|, shifted-force LJ + reaction field:
 //   g = phi_sf'(r)/r = G6 r^-8 + qq (2 k_rf - r^-3) + C1 r^-1,   G6 = a12 r^-6 + a6,
@@ -539,12 +539,22 @@ __device__ __forceinline__ void pair_wave(const SegDev* __restrict__ segs, const
                                              vjz, valid, ax, ay, az, tx, ty, tz, en);
             if (WE) eacc += N3 ? en : 0.5f * en;
             if (N3) {
-                __hip_atomic_fetch_add(rb + (F_J + 0) * RING + o, tx, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_WAVEFRONT);
-                __hip_atomic_fetch_add(rb + (F_J + 1) * RING + o, ty, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_WAVEFRONT);
-                __hip_atomic_fetch_add(rb + (F_J + 2) * RING + o, tz, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_WAVEFRONT);
+                // sum the j side over the 8 i lanes (lanes 8 apart), then the 8 lanes of
+                // i-atom 0 add it to their ring entries: one plain LDS update per entry
+                tx += lane_xor<8>(tx);
+                ty += lane_xor<8>(ty);
+                tz += lane_xor<8>(tz);
+                tx += lane_xor<16>(tx);
+                ty += lane_xor<16>(ty);
+                tz += lane_xor<16>(tz);
+                tx += lane_xor<32>(tx);
+                ty += lane_xor<32>(ty);
+                tz += lane_xor<32>(tz);
+                if (lane < 8) {
+                    rb[(F_J + 0) * RING + o] += tx;
+                    rb[(F_J + 1) * RING + o] += ty;
+                    rb[(F_J + 2) * RING + o] += tz;
+                }
             }
         }
         if (WE) {  // FP32 partial of at most 64 pair terms per lane, summed in FP64
