@@ -634,3 +634,21 @@ def test_persistent_plan_is_bit_identical(name, waves, N, mop, ctx):
     for k, (a, b) in enumerate(zip(*out)):
         assert np.array_equal(a, b), k
     say(f"[persistent] {name} waves={waves}: {len(out[0])} outputs bit-identical")
+
+
+def test_waves_per_workgroup_are_bit_identical(mop, ctx):
+    """Each i-cluster's sums do not depend on how many waves share a workgroup: plans with
+    1, 2, 4 and 8 waves per workgroup give bit-identical gradients and V_eff."""
+    s = W.cfg2()
+    N = 4
+    R, _, _ = W.random_walk_path(s, N, 41)
+    Rt = cuda(R)
+    sysm = mop.System(ctx, s)
+    out = []
+    for waves in (1, 2, 4, 8):
+        plan = mop.Plan(sysm, N, waves=waves)
+        G, v = mop.veff_grad(plan, Rt)
+        assert plan.status() == 0
+        out.append((G.cpu().numpy(), float(v[0])))
+    for G, v in out[1:]:
+        assert np.array_equal(G, out[0][0]) and v == out[0][1]
