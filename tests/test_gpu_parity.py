@@ -652,3 +652,32 @@ def test_waves_per_workgroup_are_bit_identical(mop, ctx):
         out.append((G.cpu().numpy(), float(v[0])))
     for G, v in out[1:]:
         assert np.array_equal(G, out[0][0]) and v == out[0][1]
+
+
+def test_batch_with_degenerate_paths_matches_single_calls(mop, ctx):
+    """A batch holding a 1-bead path (V_eff = U(R^1), G = -F^1), a 2-bead path and a
+    30,000-atom path of 6 beads (enough clusters for the force pass to run as two
+    launches, bead 1 of every path with energies, then the rest) gives every path the
+    gradient and V_eff of its own single-path call, bit for bit."""
+    systems = [W.water_box(30000, seed=3, rc=1.0), W.cfg2(), W.water_box(1002, seed=9, rc=1.0)]
+    Ns = [6, 1, 2]
+    plans, paths, single = [], [], []
+    for k, (s_, N) in enumerate(zip(systems, Ns)):
+        R, _, _ = W.random_walk_path(s_, N, 60 + k)
+        pl = mop.Plan(mop.System(ctx, s_), N)
+        Rt = cuda(R)
+        G, v = mop.veff_grad(pl, Rt)
+        assert pl.status() == 0
+        single.append((G.cpu().numpy(), float(v[0])))
+        plans.append(pl)
+        paths.append(Rt)
+    # the 1-bead path: V_eff is U(R^1) and G is -F^1
+    F1, U1 = mop.bead_forces(plans[1], paths[1])
+    assert abs(single[1][1] - float(U1[0])) <= 1e-12 * abs(float(U1[0]))
+    assert rel(single[1][0][0], -F1.cpu().numpy()[0].astype(np.float64)) < 1e-6
+    bt = mop.Batch(plans, Ns)
+    Gflat, v = bt.veff_grad(bt.pack(paths))
+    assert bt.status() == 0
+    for k, G in enumerate(bt.unpack(Gflat)):
+        assert np.array_equal(G.cpu().numpy(), single[k][0]), k
+        assert float(v[k]) == single[k][1], k
