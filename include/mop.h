@@ -66,7 +66,11 @@ extern "C" {
 
 /* bits of the device status word (mop_status) */
 #define MOP_DEV_NONFINITE 1 /* a force, residual or gradient component is not finite */
-#define MOP_DEV_CAPACITY 2  /* a neighbour-search buffer overflowed (re-plan) */
+#define MOP_DEV_CAPACITY 2  /* a fixed-capacity device buffer is full: the Gaussian history
+                               of a bias (re-create it with more capacity).  The neighbour
+                               search has no such buffer: candidate lists are processed in
+                               rounds, and a cluster whose recorded list overflowed is
+                               searched again. */
 #define MOP_DEV_OVERLAP 4   /* a force pass met a non-excluded pair closer than 0.01 nm
                                (overlapping atoms: FP32 pair terms of order r^-14 are then
                                meaningless; the outputs are still written) */
