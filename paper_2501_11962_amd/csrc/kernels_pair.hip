@@ -1,6 +1,7 @@
 // Pair kernels: the physical force F(R^n) (the do_force work of section 2.1) and the
 // exact Hessian-vector product H(R^n) v that replaces the finite-difference term of
-// eq. (5), for every pair bead of every path of a call in one launch.
+// eq. (5), for every pair bead of every path of a call in one launch (in two when only
+// bead 1 needs energies: see launch_pair_e).
 //
 // Work unit: one wave per 8-atom i-cluster (8 consecutive slots of one column).
 //   1. Lane-parallel over the x-y column stencil: keep columns whose rectangle lies
@@ -15,8 +16,13 @@
 //   3. Every EB (64) ring entries, EB/8 steps of 8 j-atoms x 8 i-atoms (lane = 8*i + j)
 //      evaluate the pair terms; each lane accumulates a partial sum for its i atom.
 //   4. Partial sums are reduced over the 8 j lanes.
+//   The force pass records each cluster's neighbour list (one record per candidate
+//   cluster with survivors); the Hessian pass of the same bead replays it instead of
+//   steps 1-2.
 // Launch: a flat grid (one workgroup per W clusters, k_pair) or, as a plan option, a
 // persistent grid over per-XCD work queues (k_pair_q); both run the same per-wave body.
+// Energies are a template parameter, so that kernels that need none take fewer
+// registers and hold more waves per SIMD (PAIR_WAVES).
 //
 // Two variants:
 //   N3 = 1 (opt-in): Newton's third law.  A wave takes only clusters with a larger
