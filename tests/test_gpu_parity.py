@@ -681,3 +681,37 @@ def test_batch_with_degenerate_paths_matches_single_calls(mop, ctx):
     for k, G in enumerate(bt.unpack(Gflat)):
         assert np.array_equal(G.cpu().numpy(), single[k][0]), k
         assert float(v[k]) == single[k][1], k
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+def test_graph_replay_of_fd_modes_matches_eager(mode, mop, ctx):
+    """The finite-difference modes (re-binned and shared-bin) run without host
+    synchronisation too: a captured call replays bit-identically to the eager call, with
+    eager work on the same workspace between replays."""
+    import torch
+    s = W.cfg2()
+    N = 5
+    R, _, _ = W.random_walk_path(s, N, 43)
+    plan = mop.Plan(mop.System(ctx, s), N)
+    Rt = cuda(R)
+    G = torch.empty_like(Rt)
+    v = torch.empty(1, dtype=torch.float64, device=Rt.device)
+    mop.veff_grad(plan, Rt, mode, 1e-4, G, v)
+    torch.cuda.synchronize()
+    Ge, ve = G.cpu().numpy().copy(), float(v[0])
+    g = torch.cuda.CUDAGraph()
+    cs = torch.cuda.Stream()
+    cs.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.graph(g, stream=cs):
+        ctx.set_stream()
+        mop.veff_grad(plan, Rt, mode, 1e-4, G, v)
+    ctx.set_stream()
+    torch.cuda.synchronize()
+    for k in range(3):
+        mop.veff_grad(plan, Rt + 1e-3 * (k + 1), mode, 1e-4)
+        torch.cuda.synchronize()
+        G.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(G.cpu().numpy(), Ge) and float(v[0]) == ve, k
+    assert plan.status() == 0
