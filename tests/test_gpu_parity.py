@@ -715,3 +715,41 @@ def test_graph_replay_of_fd_modes_matches_eager(mode, mop, ctx):
         torch.cuda.synchronize()
         assert np.array_equal(G.cpu().numpy(), Ge) and float(v[0]) == ve, k
     assert plan.status() == 0
+
+
+def test_graph_replay_of_bead_calls_matches_eager(mop, ctx):
+    """bead_forces (with energies) and bead_hvp captured in one graph: every replay equals
+    the eager calls bit for bit."""
+    import torch
+    s = W.cfg2()
+    B = 3
+    R, _, _ = W.random_walk_path(s, B, 47)
+    plan = mop.Plan(mop.System(ctx, s), B)
+    Rt = cuda(R)
+    Vt = cuda(np.random.default_rng(8).normal(0.0, 1e-3, R.shape))
+    F = torch.empty((B, s["Q"], 3), dtype=torch.float32, device=Rt.device)
+    U = torch.empty(B, dtype=torch.float64, device=Rt.device)
+    H = torch.empty((B, s["Q"], 3), dtype=torch.float32, device=Rt.device)
+    mop.bead_forces(plan, Rt, F, U)
+    mop.bead_hvp(plan, Rt, Vt, H)
+    torch.cuda.synchronize()
+    Fe, Ue, He = F.cpu().numpy().copy(), U.cpu().numpy().copy(), H.cpu().numpy().copy()
+    g = torch.cuda.CUDAGraph()
+    cs = torch.cuda.Stream()
+    cs.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.graph(g, stream=cs):
+        ctx.set_stream()
+        mop.bead_forces(plan, Rt, F, U)
+        mop.bead_hvp(plan, Rt, Vt, H)
+    ctx.set_stream()
+    torch.cuda.synchronize()
+    for k in range(3):
+        mop.bead_forces(plan, Rt + 1e-3 * (k + 1))
+        torch.cuda.synchronize()
+        F.zero_()
+        H.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(F.cpu().numpy(), Fe) and np.array_equal(U.cpu().numpy(), Ue), k
+        assert np.array_equal(H.cpu().numpy(), He), k
+    assert plan.status() == 0
